@@ -1,0 +1,189 @@
+"""CPU oracle for canonical-Huffman coding of uint16 quantization codes.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product library never imports,
+links or runs anything in this directory, and this directory uses nothing
+from the product library.
+
+The arithmetic lives in ``hdref.c`` (plain C, one obvious loop per
+definition); this module compiles it with gcc and wraps it with ctypes over
+numpy arrays.  See ``hdref.c`` for the passage each routine follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hdref.c")
+_LIB = os.path.join(_HERE, "libhdref.so")
+
+OK, EARG, EINFEASIBLE, ESYMBOL, ECORRUPT, ENOMEM = 0, -1, -2, -3, -4, -5
+
+
+def build(force: bool = True) -> str:
+    """Compile hdref.c into libhdref.so (gcc -O2, plain C11)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-fPIC", "-shared",
+                               _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        p = C.c_void_p
+        u32, u64 = C.c_uint32, C.c_uint64
+        L.hdref_histogram.argtypes = [p, u64, u32, p]
+        L.hdref_code_lengths.argtypes = [p, u32, u32, p]
+        L.hdref_canonical_codes.argtypes = [p, u32, p]
+        L.hdref_encode.argtypes = [p, u64, p, p, u32, u32, u32, p, u64, p, u64, p, u64, p]
+        L.hdref_decode.argtypes = [p, u64, u64, u64, p, p, u32, p]
+        L.hdref_decode_prefix.argtypes = [p, u64, u64, u64, p, p, u32, p, p]
+        L.hdref_selfsync.argtypes = [p, u64, u64, u64, p, p, u32, u32, p, p, p]
+        L.hdref_gap_backward.argtypes = [p, u64, u64, u64, p, p, u32, u32, p, p]
+        for f in ("hdref_histogram", "hdref_code_lengths", "hdref_canonical_codes", "hdref_encode",
+                  "hdref_decode", "hdref_decode_prefix", "hdref_selfsync", "hdref_gap_backward"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        super().__init__(f"{what}: oracle status {rc}")
+        self.rc = rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise OracleError(rc, what)
+
+
+def histogram(x: np.ndarray, A: int) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.uint16)
+    cnt = np.zeros(A, dtype=np.uint64)
+    _check(lib().hdref_histogram(_ptr(x), x.size, A, _ptr(cnt)), "histogram")
+    return cnt
+
+
+def code_lengths(cnt: np.ndarray, L: int) -> np.ndarray:
+    cnt = np.ascontiguousarray(cnt, dtype=np.uint64)
+    ln = np.zeros(cnt.size, dtype=np.uint8)
+    _check(lib().hdref_code_lengths(_ptr(cnt), cnt.size, L, _ptr(ln)), "code_lengths")
+    return ln
+
+
+def canonical_codes(lengths: np.ndarray) -> np.ndarray:
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    code = np.zeros(lengths.size, dtype=np.uint32)
+    _check(lib().hdref_canonical_codes(_ptr(lengths), lengths.size, _ptr(code)), "canonical_codes")
+    return code
+
+
+@dataclass
+class Encoded:
+    words: np.ndarray          # uint32[n_words], MSB-first, zero tail and 2 guard units
+    gap: np.ndarray            # uint8[K], forward gap in bits
+    chunk_counts: np.ndarray   # uint32[M]
+    n_symbols: int
+    n_bits: int
+    S: int
+    C: int
+
+    @property
+    def n_subseq(self):
+        return self.gap.size
+
+    @property
+    def n_chunks(self):
+        return self.chunk_counts.size
+
+
+def encode(x: np.ndarray, lengths: np.ndarray, codes: np.ndarray, S: int = 128, C: int = 32) -> Encoded:
+    x = np.ascontiguousarray(x, dtype=np.uint16)
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    codes = np.ascontiguousarray(codes, dtype=np.uint32)
+    A = lengths.size
+    info = np.zeros(4, dtype=np.uint64)
+    L = lib()
+    _check(L.hdref_encode(_ptr(x), x.size, _ptr(lengths), _ptr(codes), A, S, C,
+                          None, 0, None, 0, None, 0, _ptr(info)), "encode(size)")
+    B, NW, K, M = (int(v) for v in info)
+    words = np.zeros(NW, dtype=np.uint32)
+    gap = np.zeros(K, dtype=np.uint8)
+    cc = np.zeros(M, dtype=np.uint32)
+    _check(L.hdref_encode(_ptr(x), x.size, _ptr(lengths), _ptr(codes), A, S, C,
+                          _ptr(words), NW, _ptr(gap), K, _ptr(cc), M, _ptr(info)), "encode")
+    return Encoded(words, gap, cc, x.size, B, S, C)
+
+
+def decode(words: np.ndarray, n_bits: int, n: int, lengths: np.ndarray, codes: np.ndarray) -> np.ndarray:
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    codes = np.ascontiguousarray(codes, dtype=np.uint32)
+    out = np.zeros(n, dtype=np.uint16)
+    _check(lib().hdref_decode(_ptr(words), words.size, n_bits, n, _ptr(lengths), _ptr(codes),
+                              lengths.size, _ptr(out)), "decode")
+    return out
+
+
+def decode_prefix(words, n_bits, n, lengths, codes, out=None):
+    """Decodes the first n symbols (no end check); returns (symbols, end bit)."""
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    codes = np.ascontiguousarray(codes, dtype=np.uint32)
+    if out is None:
+        out = np.zeros(n, dtype=np.uint16)
+    end = np.zeros(1, dtype=np.uint64)
+    _check(lib().hdref_decode_prefix(_ptr(words), words.size, n_bits, n, _ptr(lengths), _ptr(codes),
+                                     lengths.size, _ptr(out), _ptr(end)), "decode_prefix")
+    return out, int(end[0])
+
+
+def selfsync(words, n_bits, n, lengths, codes, S):
+    """(sync_gap uint8[K], counts uint32[K], sync_bits uint32[K]) -- see hdref.c."""
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    codes = np.ascontiguousarray(codes, dtype=np.uint32)
+    K = (n_bits + S - 1) // S
+    g = np.zeros(K, dtype=np.uint8)
+    c = np.zeros(K, dtype=np.uint32)
+    b = np.zeros(K, dtype=np.uint32)
+    _check(lib().hdref_selfsync(_ptr(words), words.size, n_bits, n, _ptr(lengths), _ptr(codes),
+                                lengths.size, S, _ptr(g), _ptr(c), _ptr(b)), "selfsync")
+    return g, c, b
+
+
+def gap_backward(words, n_bits, n, lengths, codes, S):
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    codes = np.ascontiguousarray(codes, dtype=np.uint32)
+    K = (n_bits + S - 1) // S
+    g = np.zeros(K, dtype=np.int32)
+    c = np.zeros(K, dtype=np.uint32)
+    _check(lib().hdref_gap_backward(_ptr(words), words.size, n_bits, n, _ptr(lengths), _ptr(codes),
+                                    lengths.size, S, _ptr(g), _ptr(c)), "gap_backward")
+    return g, c
+
+
+def build_codebook(x: np.ndarray, A: int, L: int):
+    """histogram -> package-merge lengths -> canonical codes."""
+    ln = code_lengths(histogram(x, A), L)
+    return ln, canonical_codes(ln)
