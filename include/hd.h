@@ -1,0 +1,257 @@
+/*
+ * hd.h -- canonical-Huffman decoding of uint16 quantization-code streams on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the lossless stage of SZ-style error-bounded lossy
+ * decompression: quantization codes (fixed-length uint16 input symbols) were
+ * Huffman-coded into variable-length prefix-free codewords (paper Sec. II-B,
+ * adapted to multi-byte symbols in Sec. IV); decoding turns the codeword
+ * bitstream back into the uint16 array, whose byte size defines throughput
+ * (Table II caption: GB/s relative to the quantization codes).  Decoding stays
+ * on the device with no host transfer (Sec. I, in-memory use case).
+ *
+ * Stream format (all integers native little-endian):
+ *   words        uint32[n_words], the bitstream in 32-bit units (Sec. III-B);
+ *                stream bit i is bit (31 - i%32) of words[i/32] (MSB first);
+ *                codewords are written MSB first; bits past n_bits are 0;
+ *                n_words = n_subseq * subseq_bits / 32 + 2 (two zero guard
+ *                units so a 64-bit window at any bit < n_bits stays inside).
+ *   gap          uint8[n_subseq] (Sec. III-C, the gap array, one byte per
+ *                subsequence): gap[k] = p_k - k*S, p_k the first codeword
+ *                start at or after bit k*S, the stream end counting as a
+ *                start.  Always 0 <= gap[k] < max_len.
+ *   chunk_counts uint32[n_chunks]: codewords whose FIRST bit lies in chunk c
+ *                (subsequences [c*C, (c+1)*C)); their exclusive prefix sum is
+ *                the first output index of each chunk (Sec. III-B, step 3).
+ *   S = subseq_bits (a multiple of 32), C = chunk_subseqs,
+ *   n_subseq = ceil(n_bits / S), n_chunks = ceil(n_subseq / C).
+ *
+ * Codebooks are canonical (codes of one length are consecutive integers in
+ * symbol order, each length's first code continuing the previous length's);
+ * lengths[s] = 0 marks a symbol without a codeword.  Codes are right-aligned
+ * in uint32.  1 <= max_len <= 32, alphabet_size <= 65536.
+ *
+ * Conventions for every entry point:
+ *   - ownership: the caller owns every buffer; the only library-owned object
+ *     is hd_table (created by hd_table_create, freed by hd_table_destroy);
+ *   - errors: no exception or abort crosses this interface.  Argument and
+ *     format errors are returned synchronously.  Data-dependent faults found
+ *     while decoding on the device are reported asynchronously through the
+ *     workspace status word (hd_decode_status);
+ *   - device calls are asynchronous and ordered on the given hipStream_t
+ *     (passed as void*; NULL = the null stream).  Calls on distinct
+ *     workspaces may run concurrently; calls sharing a workspace must be
+ *     ordered by the caller.
+ */
+#ifndef HD_H
+#define HD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HD_OK = 0,
+    HD_ERR_ARG = -1,          /* bad pointer, size or parameter                  */
+    HD_ERR_INFEASIBLE = -2,   /* more used symbols than 2^max_len                */
+    HD_ERR_SYMBOL = -3,       /* symbol >= alphabet_size or without a codeword   */
+    HD_ERR_CORRUPT = -4,      /* stream/metadata inconsistent with the codebook  */
+    HD_ERR_NOMEM = -5,        /* host or device allocation failed                */
+    HD_ERR_DEVICE = -6,       /* HIP runtime error                               */
+    HD_ERR_UNSUPPORTED = -7   /* valid input this decoder does not take          */
+} hd_status;
+
+typedef enum {
+    HD_MODE_GAP = 0,          /* start each subsequence from the gap array       */
+    HD_MODE_SELF_SYNC = 1     /* find the starts by self-synchronization; reads
+                                 neither gap nor chunk_counts (may be NULL)      */
+} hd_mode;
+
+typedef struct {
+    uint32_t subseq_bits;     /* S: bits per subsequence, multiple of 32, >= 32  */
+    uint32_t chunk_subseqs;   /* C: subsequences per chunk, >= 1                 */
+} hd_layout;
+
+typedef struct {
+    uint64_t n_symbols;       /* n: decoded symbols                              */
+    uint64_t n_bits;          /* B: total codeword bits                          */
+    uint64_t n_words;         /* units in `words`, guard included                */
+    uint64_t n_subseq;        /* K = ceil(B / S)                                 */
+    uint64_t n_chunks;        /* M = ceil(K / C)                                 */
+    uint32_t subseq_bits;     /* S */
+    uint32_t chunk_subseqs;   /* C */
+    uint32_t alphabet_size;   /* A */
+    uint32_t max_len;         /* L */
+} hd_stream_info;
+
+typedef struct hd_table hd_table;
+
+/* Decode-time knobs.  Zero in any field means "choose automatically". */
+typedef struct {
+    uint32_t waves_per_group; /* wavefronts per workgroup: 4, 8 or 16             */
+    uint32_t stage_symbols;   /* LDS output staging per wavefront, in symbols,
+                                 a multiple of 64 in [256, 16384]                 */
+    uint32_t groups_per_cu;   /* persistent workgroups per compute unit           */
+    uint32_t reserved;
+} hd_tune;
+
+/* A device-resident stream.  All pointers are device memory owned by the
+ * caller; `table` must have been created for the stream's codebook. */
+typedef struct {
+    const uint32_t *words;
+    const uint8_t *gap;            /* HD_MODE_GAP only */
+    const uint32_t *chunk_counts;  /* HD_MODE_GAP only */
+    hd_stream_info info;
+    const hd_table *table;
+} hd_dstream;
+
+/* ---------------------------------------------------------------- host --- */
+
+/*
+ * Optimal length-limited code lengths and canonical codes from a histogram
+ * (Sec. II-B: a prefix-free code giving frequent symbols short codewords; the
+ * paper leaves the construction to its encoder, this library minimizes the
+ * total coded length subject to lengths <= L).
+ *   hist[A]    counts per symbol (0 = unused)                       [in]
+ *   lengths[A] code length per symbol, 0 for unused                 [out]
+ *   codes[A]   right-aligned canonical code per symbol, 0 if unused [out]
+ * Ties among optimal length vectors are broken deterministically: symbols are
+ * ranked by (count, symbol) and, at equal weight, a single symbol ranks
+ * before a merged pair.  One used symbol gets length 1; none gives an empty
+ * code.  Returns HD_ERR_INFEASIBLE when more than 2^L symbols are used,
+ * HD_ERR_ARG for A outside [1, 65536] or L outside [1, 32].  Synchronous.
+ */
+hd_status hd_build_codebook(const uint64_t *hist, uint32_t A, uint32_t L,
+                            uint8_t *lengths, uint32_t *codes);
+
+/*
+ * Reference encoder (host): packs syms[n] with the codebook into the stream
+ * format above and emits the gap array (Sec. III-C) and per-chunk codeword
+ * counts.  Two-call use: with words == NULL only *info is filled (sizes);
+ * then call again with buffers of at least info->n_words / n_subseq /
+ * n_chunks entries.  Returns HD_ERR_SYMBOL for a symbol >= A or without a
+ * codeword, HD_ERR_ARG for a bad layout (S not a positive multiple of 32,
+ * C == 0) or short buffers.  The codebook need not be canonical.  Synchronous.
+ */
+hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8_t *lengths,
+                        const uint32_t *codes, uint32_t A, uint32_t L, const hd_layout *lay,
+                        uint32_t *words, uint64_t words_cap, uint8_t *gap, uint64_t gap_cap,
+                        uint32_t *chunk_counts, uint64_t chunk_cap, hd_stream_info *info);
+
+/* --------------------------------------------------------------- device -- */
+
+/*
+ * Builds the device-resident decode table of a canonical codebook: a
+ * first-level lookup table indexed by the next `lut_bits` stream bits (0 =
+ * default, else 6..14, capped at L) giving (symbol, length) for codewords up
+ * to that length, plus per-length canonical limits and the symbol list for
+ * longer codewords.  The paper keeps its codebook in global memory and relies
+ * on the cache (Sec. IV-B); here each workgroup copies the first level and
+ * the limits into LDS.  The upload is enqueued on hip_stream; the table may
+ * be used by later work on that stream at once.  Returns HD_ERR_UNSUPPORTED
+ * for a non-canonical codebook.  *out is owned by the caller until
+ * hd_table_destroy.
+ */
+hd_status hd_table_create(const uint8_t *lengths, const uint32_t *codes, uint32_t A, uint32_t L,
+                          uint32_t lut_bits, void *hip_stream, hd_table **out);
+
+/* Frees a table (synchronizes the device first).  NULL is ignored. */
+void hd_table_destroy(hd_table *t);
+
+/* Bytes of LDS one workgroup spends on the table (first level + limits). */
+size_t hd_table_lds_bytes(const hd_table *t);
+
+/*
+ * Device workspace bytes hd_decode needs for stream s in mode m (tune may be
+ * NULL).  The workspace holds the status word and the output-index scan; it
+ * needs no initialization.
+ */
+hd_status hd_decode_workspace_size(const hd_dstream *s, hd_mode m, const hd_tune *tune,
+                                   size_t *bytes);
+
+/*
+ * Decodes one stream into out[0 .. n_symbols) (device memory).
+ * HD_MODE_GAP: each subsequence starts at k*S + gap[k] (Sec. III-C); output
+ * indices are the exclusive prefix sum of chunk_counts, refined per
+ * subsequence by a wavefront scan of decoded counts (Sec. III-B, step 3);
+ * symbols are staged in LDS and written with coalesced stores (Sec. IV-B,
+ * Algorithm 1).
+ * HD_MODE_SELF_SYNC: the sync point of every subsequence is found by
+ * decoding from the raw boundary until the path meets the previous
+ * subsequence's verified exit (Sec. III-B-2, steps 1-2), the counts found on
+ * the way are scanned (step 3) and the decode/write step is the same as in
+ * gap mode (step 4).  No gap or chunk_counts input is read.
+ * Asynchronous on hip_stream.  Returns HD_ERR_ARG / HD_ERR_UNSUPPORTED for
+ * bad arguments (including a workspace smaller than
+ * hd_decode_workspace_size), HD_ERR_DEVICE for launch failures.  Faults in
+ * the data are reported by hd_decode_status.
+ */
+hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
+                    void *workspace, size_t ws_bytes, void *hip_stream);
+
+/*
+ * hd_decode in two parts, for callers that time the phases or decode one
+ * stream repeatedly.  hd_decode_prepare enqueues the output-index phase
+ * (gap mode: the chunk-offset scan of chunk_counts; self-sync mode: the
+ * synchronization steps 1-3 of Sec. III-B-2) and leaves its result in the
+ * workspace; hd_decode_run enqueues the decode-and-write step (step 4,
+ * Sec. IV-B) reading that result.  prepare followed by run on one stream
+ * equals hd_decode; run may be repeated while the workspace is untouched.
+ * Same arguments, errors and asynchrony as hd_decode.
+ */
+hd_status hd_decode_prepare(const hd_dstream *s, hd_mode m, const hd_tune *tune, void *workspace,
+                            size_t ws_bytes, void *hip_stream);
+hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
+                        void *workspace, size_t ws_bytes, void *hip_stream);
+
+/*
+ * Workspace bytes for hd_decode_batch over n_streams streams.
+ */
+hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, uint32_t n_streams,
+                                         hd_mode m, size_t *bytes);
+
+/*
+ * Decodes n_streams independent streams, each with its own table, into
+ * outs[i] (device memory, n_symbols of stream i each) in one persistent
+ * launch (gap mode) whose workgroups pull (stream, tile) work items from a
+ * list ordered by stream; the decode table in LDS is reloaded only when the
+ * stream changes.  The paper groups sequences by compression ratio and
+ * launches one kernel per group with its own shared-memory size
+ * (Sec. IV-C, Algorithm 2); here the grouping is a host-built work list and
+ * the per-class parameters come from the autotuner (per_stream may be NULL).
+ * m must be HD_MODE_GAP.  Asynchronous; status via hd_decode_status.
+ */
+hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_streams, uint16_t *const *outs,
+                          hd_mode m, const hd_tune *tune, void *workspace, size_t ws_bytes,
+                          void *hip_stream);
+
+/*
+ * Waits for hip_stream, then reads the status word the last decode on this
+ * workspace left: HD_OK, or HD_ERR_CORRUPT when a lane met an invalid
+ * codeword, a subsequence ended off its successor's start, a chunk's decoded
+ * count differed from chunk_counts, the counts did not add up to n_symbols,
+ * or self-synchronization found no consistent sync point.
+ */
+hd_status hd_decode_status(const void *workspace, void *hip_stream);
+
+/*
+ * The raw status bits behind hd_decode_status (0 = clean; 0xffffffff when the
+ * word could not be read).  Bit 0: a gap byte beyond any codeword length;
+ * 1: a window matching no codeword; 2: a subsequence ending off its
+ * successor's start; 3: a chunk count mismatch; 4: counts not adding up to
+ * n_symbols; 5: an output index outside [0, n_symbols); 6: no consistent
+ * self-synchronization point.  Waits for hip_stream first.
+ */
+uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream);
+
+/* Static description of a status code. */
+const char *hd_status_str(hd_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HD_H */

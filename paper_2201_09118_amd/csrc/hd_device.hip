@@ -1,0 +1,881 @@
+// Device half of the library: decode tables, output-index scans and the
+// decode kernels for AMD Instinct MI355X (gfx950, wave64, 160 KiB LDS/CU).
+//
+// Hot path (gap mode), per wavefront of 64 lanes, one lane per subsequence:
+//   1. copy the tile's 32-bit units into LDS with coalesced loads;
+//   2. start at k*S + gap[k] (Sec. III-C) and count the codewords that start
+//      inside the subsequence (the paper's "redundant decoding" to learn
+//      where each thread writes, Sec. IV-C; the chunk totals come from the
+//      stream's chunk_counts, so this pass only spans one subsequence);
+//   3. wavefront exclusive scan of the counts gives each lane its output
+//      index inside the tile (Sec. III-B, step 3);
+//   4. decode again into an LDS staging tile (Sec. IV-B, Algorithm 1) and
+//      write the tile to HBM with 16-byte coalesced stores; a tile larger
+//      than the staging area is written in several passes, each lane
+//      resuming where it stopped.
+// The decode table (first level + per-length canonical limits) lives in LDS
+// for the whole persistent workgroup.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "hd.h"
+#include "hd_internal.h"
+
+using namespace hd;
+
+// ------------------------------------------------------------------------
+// Runtime helpers
+// ------------------------------------------------------------------------
+
+namespace {
+
+struct DeviceInfo {
+    int cus = 0;
+    size_t lds_per_block = 0;
+    size_t lds_per_cu = 0;
+    bool ok = false;
+};
+
+std::mutex g_dev_mu;
+DeviceInfo g_dev[64];
+
+const DeviceInfo *device_info()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceInfo &d = g_dev[dev];
+    if (!d.ok) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess)
+            return nullptr;
+        d.cus = p.multiProcessorCount;
+        d.lds_per_block = p.sharedMemPerBlock;
+        d.lds_per_cu = p.maxSharedMemoryPerMultiProcessor ? p.maxSharedMemoryPerMultiProcessor
+                                                         : p.sharedMemPerBlock;
+        d.ok = true;
+    }
+    return &d;
+}
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// Decode table
+// ------------------------------------------------------------------------
+//
+// Device image (one allocation):
+//   lut   uint32[2^k1]   entry = symbol | length << 16 for codewords of at
+//                        most k1 bits, indexed by the next k1 stream bits;
+//                        length kLenLong for a prefix of a longer codeword,
+//                        kLenBad for a prefix of no codeword;
+//   lim   uint64[33]     lim[l] = first canonical code of length l + number
+//                        of codes of length l: a window whose l-bit prefix is
+//                        below lim[l] (and whose shorter prefixes are not
+//                        below theirs) holds a codeword of length l;
+//   base  int64[33]      base[l] = index of the first length-l symbol in
+//                        `syms` minus the first code of length l;
+//   syms  uint16[n_used] used symbols sorted by (length, symbol).
+
+struct hd_table {
+    void *image = nullptr;
+    uint32_t k1 = 0, L = 0, A = 0, n_used = 0;
+    size_t lut_off = 0, lim_off = 0, base_off = 0, syms_off = 0, bytes = 0;
+    int device = 0;
+};
+
+namespace {
+
+constexpr uint32_t kDefaultLutBits = 11;
+
+struct TableView {
+    const uint32_t *lut;
+    const uint64_t *lim;
+    const int64_t *base;
+    const uint16_t *syms;
+    uint32_t k1, L;
+};
+
+inline TableView view_of(const hd_table *t)
+{
+    const char *p = static_cast<const char *>(t->image);
+    return TableView{reinterpret_cast<const uint32_t *>(p + t->lut_off),
+                     reinterpret_cast<const uint64_t *>(p + t->lim_off),
+                     reinterpret_cast<const int64_t *>(p + t->base_off),
+                     reinterpret_cast<const uint16_t *>(p + t->syms_off), t->k1, t->L};
+}
+
+__host__ __device__ __forceinline__ uint32_t table_lds_bytes(uint32_t k1)
+{
+    return (((4u << k1) + 33 * 8 + 33 * 8) + 15u) & ~15u;
+}
+
+}  // namespace
+
+extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *codes, uint32_t A,
+                                     uint32_t L, uint32_t lut_bits, void *hip_stream,
+                                     hd_table **out)
+{
+    if (!lengths || !codes || !out || A == 0 || A > 65536 || L == 0 || L > 32)
+        return HD_ERR_ARG;
+    if (lut_bits != 0 && (lut_bits < 6 || lut_bits > 14))
+        return HD_ERR_ARG;
+    *out = nullptr;
+    try {
+        std::vector<uint32_t> canon(A);
+        hd_status st = hd_canonical_codes_internal(lengths, A, L, canon.data());
+        if (st != HD_OK)
+            return st;
+        uint32_t n_used = 0;
+        for (uint32_t s = 0; s < A; ++s) {
+            if (lengths[s] && canon[s] != codes[s])
+                return HD_ERR_UNSUPPORTED;
+            n_used += lengths[s] != 0;
+        }
+        uint32_t k1 = lut_bits ? lut_bits : kDefaultLutBits;
+        k1 = std::min(k1, L);
+
+        uint64_t bl[33] = {0};
+        for (uint32_t s = 0; s < A; ++s)
+            bl[lengths[s]]++;
+        bl[0] = 0;
+        uint64_t first[34] = {0}, offs[34] = {0};
+        uint64_t c = 0, o = 0;
+        for (uint32_t l = 1; l <= 32; ++l) {
+            c = (c + bl[l - 1]) << 1;
+            first[l] = c;
+            offs[l] = o;
+            o += bl[l];
+        }
+        std::vector<uint16_t> syms(std::max<uint32_t>(n_used, 1), 0);
+        {
+            uint64_t fill[34];
+            std::memcpy(fill, offs, sizeof(fill));
+            for (uint32_t s = 0; s < A; ++s)
+                if (lengths[s])
+                    syms[fill[lengths[s]]++] = static_cast<uint16_t>(s);
+        }
+        const uint32_t nlut = 1u << k1;
+        std::vector<uint32_t> lut(nlut, kLenBad << 16);
+        for (uint32_t s = 0; s < A; ++s) {
+            const uint32_t l = lengths[s];
+            if (l > k1)
+                lut[codes[s] >> (l - k1)] = kLenLong << 16;
+        }
+        for (uint32_t s = 0; s < A; ++s) {
+            const uint32_t l = lengths[s];
+            if (l == 0 || l > k1)
+                continue;
+            const uint32_t lo = codes[s] << (k1 - l), hi = (codes[s] + 1) << (k1 - l);
+            for (uint32_t w = lo; w < hi; ++w)
+                lut[w] = s | (l << 16);
+        }
+        std::vector<uint64_t> lim(33, 0);
+        std::vector<int64_t> base(33, 0);
+        for (uint32_t l = 1; l <= 32; ++l) {
+            if (l <= L) {
+                lim[l] = first[l] + bl[l];
+                base[l] = static_cast<int64_t>(offs[l]) - static_cast<int64_t>(first[l]);
+            }
+        }
+
+        hd_table *t = new hd_table();
+        t->k1 = k1;
+        t->L = L;
+        t->A = A;
+        t->n_used = n_used;
+        t->lut_off = 0;
+        t->lim_off = align_up(size_t(4) * nlut, 16);
+        t->base_off = t->lim_off + 33 * 8;
+        t->syms_off = align_up(t->base_off + 33 * 8, 16);
+        t->bytes = align_up(t->syms_off + 2 * syms.size(), 256);
+        hipGetDevice(&t->device);
+        std::vector<unsigned char> img(t->bytes, 0);
+        std::memcpy(img.data() + t->lut_off, lut.data(), 4 * nlut);
+        std::memcpy(img.data() + t->lim_off, lim.data(), 33 * 8);
+        std::memcpy(img.data() + t->base_off, base.data(), 33 * 8);
+        std::memcpy(img.data() + t->syms_off, syms.data(), 2 * syms.size());
+        if (hipMalloc(&t->image, t->bytes) != hipSuccess) {
+            delete t;
+            return HD_ERR_NOMEM;
+        }
+        hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+        // The host image is pageable: hipMemcpyAsync from pageable memory
+        // returns once the data is staged, so `img` may be freed afterwards.
+        if (hipMemcpyAsync(t->image, img.data(), t->bytes, hipMemcpyHostToDevice, stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess) {
+            hipFree(t->image);
+            delete t;
+            return HD_ERR_DEVICE;
+        }
+        *out = t;
+        return HD_OK;
+    } catch (const std::bad_alloc &) {
+        return HD_ERR_NOMEM;
+    }
+}
+
+extern "C" void hd_table_destroy(hd_table *t)
+{
+    if (!t)
+        return;
+    if (t->image) {
+        hipDeviceSynchronize();
+        hipFree(t->image);
+    }
+    delete t;
+}
+
+extern "C" size_t hd_table_lds_bytes(const hd_table *t)
+{
+    return t ? table_lds_bytes(t->k1) : 0;
+}
+
+// ------------------------------------------------------------------------
+// Device primitives
+// ------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, kWave);
+        if (lane >= d)
+            v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1)
+        v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Orders this wavefront's LDS writes before its later LDS reads by other
+// lanes (LDS traffic of one wavefront is processed in order; this keeps the
+// compiler from moving accesses across the point).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 32 stream bits starting at relative bit r, from the LDS copy T of the
+// tile's units where T[i] holds unit (first unit of the tile) - 1 + i.
+// With q = r + 31, the bits sit in the unit pair (T[q>>5], T[q>>5 + 1])
+// shifted right by (-r) mod 32 = (~q) mod 32.
+__device__ __forceinline__ uint32_t window_at(const uint32_t *T, uint32_t q)
+{
+    const uint32_t i = q >> 5;
+    return __builtin_amdgcn_alignbit(T[i], T[i + 1], ~q);
+}
+
+// Codewords longer than the first level: canonical per-length limits.
+__device__ __noinline__ uint32_t decode_long(uint32_t v, uint32_t k1, uint32_t L,
+                                             const uint64_t *lim, const int64_t *base,
+                                             const uint16_t *syms, uint32_t *len_out)
+{
+    for (uint32_t l = k1 + 1; l <= L; ++l) {
+        const uint64_t c = static_cast<uint64_t>(v) >> (32 - l);
+        if (c < lim[l]) {
+            *len_out = l;
+            return syms[static_cast<int64_t>(c) + base[l]];
+        }
+    }
+    *len_out = 0;
+    return 0;
+}
+
+struct SmemTable {
+    uint32_t *lut;
+    uint64_t *lim;
+    int64_t *base;
+};
+
+__device__ __forceinline__ SmemTable carve_table(unsigned char *smem, uint32_t k1)
+{
+    SmemTable t;
+    t.lut = reinterpret_cast<uint32_t *>(smem);
+    t.lim = reinterpret_cast<uint64_t *>(smem + (size_t(4) << k1));
+    t.base = reinterpret_cast<int64_t *>(smem + (size_t(4) << k1) + 33 * 8);
+    return t;
+}
+
+__device__ __forceinline__ void load_table(const SmemTable &t, const TableView &g)
+{
+    const uint32_t nlut = 1u << g.k1;
+    const uint4 *src = reinterpret_cast<const uint4 *>(g.lut);
+    uint4 *dst = reinterpret_cast<uint4 *>(t.lut);
+    for (uint32_t i = threadIdx.x; i < nlut / 4; i += blockDim.x)
+        dst[i] = src[i];
+    for (uint32_t i = threadIdx.x; i < (nlut & 3u); i += blockDim.x)
+        t.lut[(nlut & ~3u) + i] = g.lut[(nlut & ~3u) + i];
+    if (threadIdx.x < 33) {
+        t.lim[threadIdx.x] = g.lim[threadIdx.x];
+        t.base[threadIdx.x] = g.base[threadIdx.x];
+    }
+}
+
+// One codeword at relative bit position q - 31.  Returns the symbol and
+// advances q by the codeword length; an invalid window advances by one bit
+// and raises kErrBadCode (so every loop still terminates).
+__device__ __forceinline__ uint32_t decode_one(const uint32_t *T, uint32_t &q, const SmemTable &st,
+                                               const TableView &g, uint32_t sh, uint32_t &err)
+{
+    const uint32_t v = window_at(T, q);
+    const uint32_t e = st.lut[v >> sh];
+    uint32_t len = e >> 16;
+    uint32_t sym = e & 0xffffu;
+    if (len - 1u >= g.k1) {   // kLenLong (0) or kLenBad (63)
+        sym = decode_long(v, g.k1, g.L, st.lim, st.base, g.syms, &len);
+        if (len == 0) {
+            err |= kErrBadCode;
+            len = 1;
+        }
+    }
+    q += len;
+    return sym;
+}
+
+// ------------------------------------------------------------------------
+// Output-index scan over chunks (Sec. III-B, step 3)
+// ------------------------------------------------------------------------
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPerThread = 8;
+constexpr int kScanBlock = kScanThreads * kScanPerThread;
+
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh)
+{
+    v = wave_sum_u64(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+        sh[w] = v;
+    __syncthreads();
+    uint64_t r = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i)
+        r += sh[i];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__restrict__ cc,
+                                                              uint64_t M, uint64_t *partial,
+                                                              uint32_t *status)
+{
+    __shared__ uint64_t sh[kScanThreads / 64];
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *status = 0;
+    const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * kScanBlock;
+    uint64_t s = 0;
+    for (int i = 0; i < kScanPerThread; ++i) {
+        const uint64_t c = b0 + static_cast<uint64_t>(i) * kScanThreads + threadIdx.x;
+        if (c < M)
+            s += cc[c];
+    }
+    s = block_sum_u64(s, sh);
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = s;
+}
+
+// off[c] = sum of cc[0..c) for c in [0, M]; flags kErrTotal when off[M] != n.
+__global__ __launch_bounds__(kScanThreads) void k_scan_finish(const uint32_t *__restrict__ cc,
+                                                              uint64_t M,
+                                                              const uint64_t *__restrict__ partial,
+                                                              uint64_t *off, uint64_t n,
+                                                              uint32_t *status)
+{
+    __shared__ uint64_t sh[kScanThreads / 64];
+    __shared__ uint64_t tsum[kScanThreads];
+    uint64_t pre = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += blockDim.x)
+        pre += partial[i];
+    pre = block_sum_u64(pre, sh);
+
+    const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * kScanBlock;
+    const uint64_t my0 = b0 + static_cast<uint64_t>(threadIdx.x) * kScanPerThread;
+    uint32_t v[kScanPerThread];
+    uint64_t s = 0;
+    for (int i = 0; i < kScanPerThread; ++i) {
+        v[i] = (my0 + i < M) ? cc[my0 + i] : 0u;
+        s += v[i];
+    }
+    tsum[threadIdx.x] = s;
+    __syncthreads();
+    // exclusive scan of the 256 thread sums (Hillis-Steele in shared memory)
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        const uint64_t o = threadIdx.x >= (unsigned)d ? tsum[threadIdx.x - d] : 0;
+        __syncthreads();
+        tsum[threadIdx.x] += o;
+        __syncthreads();
+    }
+    uint64_t run = pre + tsum[threadIdx.x] - s;
+    for (int i = 0; i < kScanPerThread; ++i) {
+        if (my0 + i < M)
+            off[my0 + i] = run;
+        run += v[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
+        const uint64_t total = pre + tsum[kScanThreads - 1];
+        off[M] = total;
+        if (total != n)
+            atomicOr(status, kErrTotal);
+    }
+}
+
+// ------------------------------------------------------------------------
+// Gap-mode decode (persistent, one lane per subsequence)
+// ------------------------------------------------------------------------
+
+struct GapArgs {
+    const uint32_t *words;
+    const uint8_t *gap;
+    const uint64_t *chunk_off;   // [M + 1]
+    uint16_t *out;
+    uint32_t *status;
+    TableView tab;
+    uint64_t n, B, K, n_words;
+    uint32_t S, C, stage;        // stage: staging symbols per wave (multiple of 64)
+};
+
+// LDS of one wave's private area: the unit copy T[0 .. 2S + 2) placed at
+// word 3 so that T + 1 is 16-byte aligned (2S + 8 words, a multiple of 16
+// bytes), then the staging tile.
+__host__ __device__ __forceinline__ uint32_t wave_units_bytes(uint32_t S)
+{
+    return (2 * S + 8) * 4;
+}
+
+__host__ __device__ __forceinline__ uint32_t wave_area_bytes(uint32_t S, uint32_t stage)
+{
+    return wave_units_bytes(S) + 2 * stage;
+}
+
+template <int WPG>
+__global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const TableView &g = a.tab;
+    const SmemTable st = carve_table(smem, g.k1);
+    load_table(st, g);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const uint32_t S = a.S;
+    const uint32_t wps = S >> 5;
+    unsigned char *area = smem + table_lds_bytes(g.k1) + wv * wave_area_bytes(S, a.stage);
+    uint32_t *T = reinterpret_cast<uint32_t *>(area) + 3;
+    uint16_t *stage = reinterpret_cast<uint16_t *>(area + wave_units_bytes(S));
+    const uint32_t sh = 32 - g.k1;
+    const uint32_t nT = 2 * S + 2;
+    const uint32_t PB = a.stage - 8;
+
+    uint32_t err = 0;
+    const uint64_t ntiles = (a.K + 63) >> 6;
+    for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv; t < ntiles;
+         t += static_cast<uint64_t>(gridDim.x) * WPG) {
+        const uint64_t k0 = t << 6;
+        const uint64_t w0 = k0 * wps;                 // first unit of the tile
+        // 1. units [w0 - 1, w0 + 2S + 1) -> T[0 .. 2S + 2)
+        {
+            const uint64_t nfull = 2 * S;              // units w0 .. w0 + 2S
+            if (w0 + nfull <= a.n_words) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(a.words + w0);
+                uint4 *dst = reinterpret_cast<uint4 *>(T + 1);
+                for (uint32_t i = lane; i < nfull / 4; i += 64)
+                    dst[i] = src[i];
+            } else {
+                for (uint32_t i = lane; i < nfull; i += 64)
+                    T[1 + i] = (w0 + i < a.n_words) ? a.words[w0 + i] : 0u;
+            }
+            if (lane == 0)
+                T[0] = w0 ? a.words[w0 - 1] : 0u;
+            if (lane == 1)
+                T[nT - 1] = (w0 + nfull < a.n_words) ? a.words[w0 + nfull] : 0u;
+        }
+        wave_lds_sync();
+
+        // 2. count pass
+        const uint64_t k = k0 + lane;
+        const bool act = k < a.K;
+        const uint64_t bit0 = k0 * S;
+        uint32_t gk = act ? a.gap[k] : 0u;
+        uint32_t rs = lane * S + gk;
+        uint32_t re = 0;
+        if (act) {
+            const uint64_t e = (k + 1) * S < a.B ? (k + 1) * S : a.B;
+            re = static_cast<uint32_t>(e - bit0);
+        }
+        if (gk >= 32) {
+            err |= kErrGapRange;
+            rs = re;
+        }
+        if (rs > re)
+            rs = re;
+        uint32_t q = rs + 31;
+        const uint32_t qe = re + 31;
+        uint32_t cnt = 0;
+        while (q < qe) {
+            decode_one(T, q, st, g, sh, err);
+            ++cnt;
+        }
+        // the walk must stop exactly on the next subsequence's start
+        {
+            uint32_t gn = __shfl_down(gk, 1, 64);
+            if (lane == 63)
+                gn = (k + 1 < a.K) ? a.gap[k + 1] : 0u;
+            if (act) {
+                const uint64_t expect = (k + 1 < a.K) ? (uint64_t)(lane + 1) * S + gn : a.B - bit0;
+                if ((uint64_t)(q - 31) != expect)
+                    err |= kErrLaneEnd;
+            }
+        }
+
+        // 3. output indices
+        const uint32_t incl = wave_incl_scan(cnt, lane);
+        const uint32_t excl = incl - cnt;
+        const uint32_t total = __shfl(incl, 63, 64);
+        const uint64_t gbase = a.chunk_off[k0 / a.C];
+        {
+            const uint32_t cl = lane % a.C;
+            const uint32_t excl_first = __shfl(excl, lane - cl, 64);
+            if (act && (cl == a.C - 1 || k == a.K - 1)) {
+                const uint64_t c = k / a.C;
+                if (gbase + excl_first != a.chunk_off[c] ||
+                    gbase + incl != a.chunk_off[c + 1])
+                    err |= kErrChunkSum;
+            }
+        }
+
+        // 4. decode into LDS staging, flush with 16-byte stores
+        const uint32_t a0 = static_cast<uint32_t>(gbase & 7);
+        q = rs + 31;
+        uint32_t j = 0;
+        for (uint32_t pb = 0; pb < total; pb += PB) {
+            const uint32_t lim_rel = pb + PB;
+            const uint32_t jmax = lim_rel > excl ? min(cnt, lim_rel - excl) : 0u;
+            // dst index of symbol j: a0 + excl + j - pb (>= a0 whenever j < jmax)
+            uint16_t *dst = stage + (static_cast<int32_t>(a0 + excl) - static_cast<int32_t>(pb));
+            while (j < jmax) {
+                const uint32_t s = decode_one(T, q, st, g, sh, err);
+                dst[j] = static_cast<uint16_t>(s);
+                ++j;
+            }
+            wave_lds_sync();
+            uint64_t g0 = gbase + pb;
+            uint64_t g1 = gbase + min(lim_rel, total);
+            if (g1 > a.n) {
+                err |= kErrOutRange;
+                g1 = a.n;
+            }
+            if (g0 < g1) {
+                const uint64_t gb0 = g0 & ~uint64_t(7);
+                const uint32_t ngroups = static_cast<uint32_t>((g1 - gb0 + 7) >> 3);
+                for (uint32_t gi = lane; gi < ngroups; gi += 64) {
+                    const uint64_t gs = gb0 + 8ull * gi;
+                    if (gs >= g0 && gs + 8 <= g1) {
+                        *reinterpret_cast<uint4 *>(a.out + gs) =
+                            *reinterpret_cast<const uint4 *>(stage + 8 * gi);
+                    } else {
+                        for (uint32_t e = 0; e < 8; ++e)
+                            if (gs + e >= g0 && gs + e < g1)
+                                a.out[gs + e] = stage[8 * gi + e];
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+    if (err)
+        atomicOr(a.status, err);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// Host entry points
+// ------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kWsHeader = 256;          // status word + padding
+
+struct Plan {
+    uint32_t wpg, stage, groups_per_cu;
+    uint32_t lds_bytes;
+    uint32_t grid;
+};
+
+hd_status check_stream(const hd_dstream *s, hd_mode m)
+{
+    if (!s || !s->table)
+        return HD_ERR_ARG;
+    const hd_stream_info &i = s->info;
+    const hd_table *t = s->table;
+    if (i.subseq_bits < 32 || i.subseq_bits % 32 != 0 || i.subseq_bits > 4096)
+        return i.subseq_bits % 32 ? HD_ERR_ARG : HD_ERR_UNSUPPORTED;
+    if (i.chunk_subseqs == 0)
+        return HD_ERR_ARG;
+    if (i.alphabet_size != t->A || i.max_len != t->L)
+        return HD_ERR_ARG;
+    const uint64_t K = ceil_div(i.n_bits, i.subseq_bits);
+    if (i.n_subseq != K || i.n_chunks != ceil_div(K, i.chunk_subseqs))
+        return HD_ERR_ARG;
+    if (i.n_words < K * (i.subseq_bits / 32) + 2)
+        return HD_ERR_ARG;
+    if (i.n_bits > i.n_symbols * uint64_t(i.max_len) || i.n_bits < i.n_symbols)
+        return HD_ERR_CORRUPT;
+    if (K && !s->words)
+        return HD_ERR_ARG;
+    if (m == HD_MODE_GAP) {
+        if (64 % i.chunk_subseqs != 0)
+            return HD_ERR_UNSUPPORTED;
+        if (K && (!s->gap || !s->chunk_counts))
+            return HD_ERR_ARG;
+    } else if (m != HD_MODE_SELF_SYNC) {
+        return HD_ERR_ARG;
+    }
+    return HD_OK;
+}
+
+hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
+{
+    const DeviceInfo *dev = device_info();
+    if (!dev)
+        return HD_ERR_DEVICE;
+    p->wpg = tune && tune->waves_per_group ? tune->waves_per_group : 8;
+    p->stage = tune && tune->stage_symbols ? tune->stage_symbols : 2048;
+    if (p->wpg != 4 && p->wpg != 8 && p->wpg != 16)
+        return HD_ERR_ARG;
+    if (p->stage < 256 || p->stage > 16384 || p->stage % 64)
+        return HD_ERR_ARG;
+    const uint32_t S = s->info.subseq_bits;
+    p->lds_bytes = table_lds_bytes(s->table->k1) + p->wpg * wave_area_bytes(S, p->stage);
+    if (p->lds_bytes > dev->lds_per_block)
+        return HD_ERR_UNSUPPORTED;
+    uint32_t fit = static_cast<uint32_t>(dev->lds_per_cu / p->lds_bytes);
+    fit = std::max<uint32_t>(1, std::min<uint32_t>(fit, 32 / p->wpg));
+    p->groups_per_cu = tune && tune->groups_per_cu ? std::min(tune->groups_per_cu, fit) : fit;
+    const uint64_t ntiles = ceil_div(s->info.n_subseq, 64);
+    const uint64_t want = ceil_div(ntiles, p->wpg);
+    const uint64_t cap = uint64_t(dev->cus) * p->groups_per_cu;
+    p->grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min(want, cap)));
+    return HD_OK;
+}
+
+size_t gap_ws_bytes(uint64_t M)
+{
+    const uint64_t nblk = std::max<uint64_t>(1, ceil_div(M, kScanBlock));
+    return kWsHeader + align_up(8 * (M + 1), 256) + align_up(8 * nblk, 256);
+}
+
+template <int WPG>
+hd_status launch_gap(const GapArgs &a, const Plan &p, hipStream_t stream)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_gap<WPG>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(device_info()->lds_per_block)) != hipSuccess)
+            return HD_ERR_DEVICE;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_decode_gap<WPG>, dim3(p.grid), dim3(WPG * 64), p.lds_bytes, stream, a);
+    return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
+}
+
+// Enqueues the chunk-offset scan: off[0..M] from chunk_counts.
+hd_status enqueue_chunk_scan(const uint32_t *cc, uint64_t M, uint64_t n, uint64_t *off,
+                             uint64_t *partial, uint32_t *status, hipStream_t stream)
+{
+    const uint64_t nblk = std::max<uint64_t>(1, ceil_div(M, kScanBlock));
+    if (nblk > 0x7fffffffu)
+        return HD_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kScanThreads), 0, stream, cc, M, partial,
+                       status);
+    hipLaunchKernelGGL(k_scan_finish, dim3(nblk), dim3(kScanThreads), 0, stream, cc, M, partial,
+                       off, n, status);
+    return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
+}
+
+}  // namespace
+
+extern "C" hd_status hd_decode_workspace_size(const hd_dstream *s, hd_mode m, const hd_tune *tune,
+                                              size_t *bytes)
+{
+    (void)tune;
+    if (!bytes)
+        return HD_ERR_ARG;
+    hd_status st = check_stream(s, m);
+    if (st != HD_OK)
+        return st;
+    if (m == HD_MODE_GAP) {
+        *bytes = gap_ws_bytes(s->info.n_chunks);
+        return HD_OK;
+    }
+    return HD_ERR_UNSUPPORTED;
+}
+
+namespace {
+
+struct WsView {
+    uint32_t *status;
+    uint64_t *off;       // [M + 1] output index of each chunk
+    uint64_t *partial;   // scan partials
+};
+
+WsView ws_view(void *workspace, uint64_t M)
+{
+    char *ws = static_cast<char *>(workspace);
+    WsView v;
+    v.status = reinterpret_cast<uint32_t *>(ws);
+    v.off = reinterpret_cast<uint64_t *>(ws + kWsHeader);
+    v.partial = reinterpret_cast<uint64_t *>(ws + kWsHeader + align_up(8 * (M + 1), 256));
+    return v;
+}
+
+hd_status check_call(const hd_dstream *s, hd_mode m, const hd_tune *tune, void *workspace,
+                     size_t ws_bytes)
+{
+    hd_status st = check_stream(s, m);
+    if (st != HD_OK)
+        return st;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 ||
+        reinterpret_cast<uintptr_t>(s->words) % 16 != 0)
+        return HD_ERR_ARG;
+    size_t need = 0;
+    st = hd_decode_workspace_size(s, m, tune, &need);
+    if (st != HD_OK)
+        return st;
+    return ws_bytes < need ? HD_ERR_ARG : HD_OK;
+}
+
+}  // namespace
+
+extern "C" hd_status hd_decode_prepare(const hd_dstream *s, hd_mode m, const hd_tune *tune,
+                                       void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    hd_status st = check_call(s, m, tune, workspace, ws_bytes);
+    if (st != HD_OK)
+        return st;
+    if (m != HD_MODE_GAP)
+        return HD_ERR_UNSUPPORTED;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const hd_stream_info &i = s->info;
+    const WsView w = ws_view(workspace, i.n_chunks);
+    return enqueue_chunk_scan(s->chunk_counts, i.n_chunks, i.n_symbols, w.off, w.partial, w.status,
+                              stream);
+}
+
+extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
+                                   void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    hd_status st = check_call(s, m, tune, workspace, ws_bytes);
+    if (st != HD_OK)
+        return st;
+    if ((s->info.n_symbols && !out) || reinterpret_cast<uintptr_t>(out) % 16 != 0)
+        return HD_ERR_ARG;
+    if (m != HD_MODE_GAP)
+        return HD_ERR_UNSUPPORTED;
+    const hd_stream_info &i = s->info;
+    if (i.n_subseq == 0)
+        return HD_OK;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const WsView w = ws_view(workspace, i.n_chunks);
+    Plan p;
+    st = make_plan(s, tune, &p);
+    if (st != HD_OK)
+        return st;
+    GapArgs a;
+    a.words = s->words;
+    a.gap = s->gap;
+    a.chunk_off = w.off;
+    a.out = out;
+    a.status = w.status;
+    a.tab = view_of(s->table);
+    a.n = i.n_symbols;
+    a.B = i.n_bits;
+    a.K = i.n_subseq;
+    a.n_words = i.n_words;
+    a.S = i.subseq_bits;
+    a.C = i.chunk_subseqs;
+    a.stage = p.stage;
+    switch (p.wpg) {
+    case 4: return launch_gap<4>(a, p, stream);
+    case 8: return launch_gap<8>(a, p, stream);
+    default: return launch_gap<16>(a, p, stream);
+    }
+}
+
+extern "C" hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
+                               void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    hd_status st = check_call(s, m, tune, workspace, ws_bytes);
+    if (st != HD_OK)
+        return st;
+    if ((s->info.n_symbols && !out) || reinterpret_cast<uintptr_t>(out) % 16 != 0)
+        return HD_ERR_ARG;
+    st = hd_decode_prepare(s, m, tune, workspace, ws_bytes, hip_stream);
+    if (st != HD_OK)
+        return st;
+    return hd_decode_run(s, out, m, tune, workspace, ws_bytes, hip_stream);
+}
+
+extern "C" hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, uint32_t n_streams,
+                                                    hd_mode m, size_t *bytes)
+{
+    (void)streams; (void)n_streams; (void)m; (void)bytes;
+    return HD_ERR_UNSUPPORTED;
+}
+
+extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_streams,
+                                     uint16_t *const *outs, hd_mode m, const hd_tune *tune,
+                                     void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    (void)streams; (void)n_streams; (void)outs; (void)m; (void)tune; (void)workspace;
+    (void)ws_bytes; (void)hip_stream;
+    return HD_ERR_UNSUPPORTED;
+}
+
+extern "C" uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream)
+{
+    if (!workspace)
+        return 0xffffffffu;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (hipStreamSynchronize(stream) != hipSuccess)
+        return 0xffffffffu;
+    uint32_t v = 0;
+    if (hipMemcpy(&v, workspace, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+        return 0xffffffffu;
+    return v;
+}
+
+extern "C" hd_status hd_decode_status(const void *workspace, void *hip_stream)
+{
+    if (!workspace)
+        return HD_ERR_ARG;
+    const uint32_t v = hd_decode_status_bits(workspace, hip_stream);
+    if (v == 0xffffffffu)
+        return HD_ERR_DEVICE;
+    return v ? HD_ERR_CORRUPT : HD_OK;
+}

@@ -1,0 +1,297 @@
+"""Python binding of libhd, the C-ABI declared in include/hd.h.
+
+Argument marshalling only: host arrays are numpy, device buffers are torch
+tensors (PyTorch supplies device memory and HIP streams; every step of the
+decode runs in the library's own kernels).  The functions keep the C names
+without the ``hd_`` prefix.  When libhd.so is missing this module raises at
+import time -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhd.so")
+
+OK, ERR_ARG, ERR_INFEASIBLE, ERR_SYMBOL, ERR_CORRUPT, ERR_NOMEM, ERR_DEVICE, ERR_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+MODE_GAP, MODE_SELF_SYNC = 0, 1
+
+# Header declarations (name -> (restype, argtypes)); the CPU test suite checks
+# that this list, include/hd.h and the library's exports agree.
+_vp, _u32, _u64, _sz = C.c_void_p, C.c_uint32, C.c_uint64, C.c_size_t
+SIGNATURES = {
+    "hd_build_codebook": (C.c_int, [_vp, _u32, _u32, _vp, _vp]),
+    "hd_encode_ref": (C.c_int, [_vp, _u64, _vp, _vp, _u32, _u32, _vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp]),
+    "hd_table_create": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _vp, C.POINTER(_vp)]),
+    "hd_table_destroy": (None, [_vp]),
+    "hd_table_lds_bytes": (_sz, [_vp]),
+    "hd_decode_workspace_size": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(_sz)]),
+    "hd_decode": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp, _sz, _vp]),
+    "hd_decode_prepare": (C.c_int, [_vp, C.c_int, _vp, _vp, _sz, _vp]),
+    "hd_decode_run": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp, _sz, _vp]),
+    "hd_decode_batch_workspace_size": (C.c_int, [_vp, _u32, C.c_int, C.POINTER(_sz)]),
+    "hd_decode_batch": (C.c_int, [_vp, _u32, _vp, C.c_int, _vp, _vp, _sz, _vp]),
+    "hd_decode_status": (C.c_int, [_vp, _vp]),
+    "hd_decode_status_bits": (_u32, [_vp, _vp]),
+    "hd_status_str": (C.c_char_p, [C.c_int]),
+}
+
+
+class HDError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+        self.status = status
+
+
+class Layout(C.Structure):
+    _fields_ = [("subseq_bits", C.c_uint32), ("chunk_subseqs", C.c_uint32)]
+
+
+class StreamInfo(C.Structure):
+    _fields_ = [("n_symbols", C.c_uint64), ("n_bits", C.c_uint64), ("n_words", C.c_uint64),
+                ("n_subseq", C.c_uint64), ("n_chunks", C.c_uint64), ("subseq_bits", C.c_uint32),
+                ("chunk_subseqs", C.c_uint32), ("alphabet_size", C.c_uint32), ("max_len", C.c_uint32)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("waves_per_group", C.c_uint32), ("stage_symbols", C.c_uint32),
+                ("groups_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class DStream(C.Structure):
+    _fields_ = [("words", C.c_void_p), ("gap", C.c_void_p), ("chunk_counts", C.c_void_p),
+                ("info", StreamInfo), ("table", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2201_09118_amd.build` "
+                              "(hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+lib()   # fail loudly at import when the extension is missing
+
+
+def status_str(st: int) -> str:
+    return lib().hd_status_str(int(st)).decode()
+
+
+def _check(st, what):
+    if st != OK:
+        raise HDError(st, what)
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# ----------------------------------------------------------------- host ---
+
+def build_codebook(hist: np.ndarray, L: int):
+    """hist uint64[A] -> (lengths uint8[A], codes uint32[A])."""
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    A = hist.size
+    ln = np.zeros(A, np.uint8)
+    cd = np.zeros(A, np.uint32)
+    _check(lib().hd_build_codebook(_np_ptr(hist), A, L, _np_ptr(ln), _np_ptr(cd)), "hd_build_codebook")
+    return ln, cd
+
+
+@dataclass
+class HostStream:
+    words: np.ndarray
+    gap: np.ndarray
+    chunk_counts: np.ndarray
+    info: StreamInfo
+
+    @property
+    def n_symbols(self):
+        return int(self.info.n_symbols)
+
+    @property
+    def n_bits(self):
+        return int(self.info.n_bits)
+
+
+def encode_ref(syms: np.ndarray, lengths: np.ndarray, codes: np.ndarray, L: int,
+               S: int = 128, Cc: int = 32) -> HostStream:
+    syms = np.ascontiguousarray(syms, dtype=np.uint16)
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    codes = np.ascontiguousarray(codes, dtype=np.uint32)
+    lay = Layout(S, Cc)
+    info = StreamInfo()
+    L_ = lib()
+    _check(L_.hd_encode_ref(_np_ptr(syms), syms.size, _np_ptr(lengths), _np_ptr(codes), lengths.size, L,
+                            C.byref(lay), None, 0, None, 0, None, 0, C.byref(info)), "hd_encode_ref(size)")
+    words = np.zeros(info.n_words, np.uint32)
+    gap = np.zeros(info.n_subseq, np.uint8)
+    cc = np.zeros(info.n_chunks, np.uint32)
+    _check(L_.hd_encode_ref(_np_ptr(syms), syms.size, _np_ptr(lengths), _np_ptr(codes), lengths.size, L,
+                            C.byref(lay), _np_ptr(words), words.size, _np_ptr(gap), gap.size, _np_ptr(cc),
+                            cc.size, C.byref(info)), "hd_encode_ref")
+    return HostStream(words, gap, cc, info)
+
+
+# --------------------------------------------------------------- device ---
+
+class Table:
+    """Device decode table (hd_table_create / hd_table_destroy)."""
+
+    def __init__(self, lengths: np.ndarray, codes: np.ndarray, L: int, lut_bits: int = 0, stream=None):
+        lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+        codes = np.ascontiguousarray(codes, dtype=np.uint32)
+        self._h = C.c_void_p()
+        _check(lib().hd_table_create(_np_ptr(lengths), _np_ptr(codes), lengths.size, L, lut_bits,
+                                     _stream_handle(stream), C.byref(self._h)), "hd_table_create")
+        self.A, self.L = lengths.size, L
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def lds_bytes(self) -> int:
+        return int(lib().hd_table_lds_bytes(self._h))
+
+    def close(self):
+        if self._h:
+            lib().hd_table_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class DeviceStream:
+    """A stream resident in device memory (torch tensors) plus its table."""
+    words: object          # torch int32 tensor (bit pattern of the uint32 units)
+    gap: object            # torch uint8 tensor or None
+    chunk_counts: object   # torch int32 tensor or None
+    info: StreamInfo
+    table: Table
+
+    @classmethod
+    def from_host(cls, hs: HostStream, table: Table, device="cuda", with_gap=True):
+        import torch
+        w = torch.from_numpy(hs.words.view(np.int32)).to(device)
+        g = torch.from_numpy(hs.gap).to(device) if with_gap else None
+        c = torch.from_numpy(hs.chunk_counts.view(np.int32)).to(device) if with_gap else None
+        info = StreamInfo()
+        C.pointer(info)[0] = hs.info
+        return cls(w, g, c, info, table)
+
+    def as_c(self) -> DStream:
+        d = DStream()
+        d.words = self.words.data_ptr() if self.words is not None and self.words.numel() else None
+        d.gap = self.gap.data_ptr() if self.gap is not None and self.gap.numel() else None
+        d.chunk_counts = (self.chunk_counts.data_ptr()
+                          if self.chunk_counts is not None and self.chunk_counts.numel() else None)
+        d.info = self.info
+        d.table = self.table.handle
+        return d
+
+    @property
+    def n_symbols(self):
+        return int(self.info.n_symbols)
+
+
+def _tune_ptr(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, dict):
+        tune = Tune(tune.get("waves_per_group", 0), tune.get("stage_symbols", 0),
+                    tune.get("groups_per_cu", 0), 0)
+    return C.byref(tune)
+
+
+def decode_workspace_size(ds: DeviceStream, mode: int = MODE_GAP, tune=None) -> int:
+    d = ds.as_c()
+    n = C.c_size_t()
+    _check(lib().hd_decode_workspace_size(C.byref(d), mode, _tune_ptr(tune), C.byref(n)),
+           "hd_decode_workspace_size")
+    return int(n.value)
+
+
+def alloc_workspace(nbytes: int, device="cuda"):
+    import torch
+    return torch.empty(max(256, nbytes), dtype=torch.uint8, device=device)
+
+
+def decode(ds: DeviceStream, out, mode: int = MODE_GAP, tune=None, workspace=None, stream=None):
+    """Enqueues hd_decode; returns the workspace (for decode_status)."""
+    d = ds.as_c()
+    if workspace is None:
+        workspace = alloc_workspace(decode_workspace_size(ds, mode, tune), out.device)
+    _check(lib().hd_decode(C.byref(d), _dev_ptr(out), mode, _tune_ptr(tune), _dev_ptr(workspace),
+                           workspace.numel(), _stream_handle(stream)), "hd_decode")
+    return workspace
+
+
+def decode_prepare(ds: DeviceStream, workspace, mode: int = MODE_GAP, tune=None, stream=None):
+    d = ds.as_c()
+    _check(lib().hd_decode_prepare(C.byref(d), mode, _tune_ptr(tune), _dev_ptr(workspace), workspace.numel(),
+                                   _stream_handle(stream)), "hd_decode_prepare")
+
+
+def decode_run(ds: DeviceStream, out, workspace, mode: int = MODE_GAP, tune=None, stream=None):
+    d = ds.as_c()
+    _check(lib().hd_decode_run(C.byref(d), _dev_ptr(out), mode, _tune_ptr(tune), _dev_ptr(workspace),
+                               workspace.numel(), _stream_handle(stream)), "hd_decode_run")
+
+
+def decode_batch_workspace_size(streams, mode: int = MODE_GAP) -> int:
+    arr = (DStream * len(streams))(*[s.as_c() for s in streams])
+    n = C.c_size_t()
+    _check(lib().hd_decode_batch_workspace_size(arr, len(streams), mode, C.byref(n)),
+           "hd_decode_batch_workspace_size")
+    return int(n.value)
+
+
+def decode_batch(streams, outs, mode: int = MODE_GAP, tune=None, workspace=None, stream=None):
+    arr = (DStream * len(streams))(*[s.as_c() for s in streams])
+    optrs = (C.c_void_p * len(outs))(*[o.data_ptr() if o.numel() else None for o in outs])
+    if workspace is None:
+        workspace = alloc_workspace(decode_batch_workspace_size(streams, mode), outs[0].device)
+    _check(lib().hd_decode_batch(arr, len(streams), optrs, mode, _tune_ptr(tune), _dev_ptr(workspace),
+                                 workspace.numel(), _stream_handle(stream)), "hd_decode_batch")
+    return workspace
+
+
+def decode_status(workspace, stream=None) -> int:
+    return int(lib().hd_decode_status(_dev_ptr(workspace), _stream_handle(stream)))
+
+
+def decode_status_bits(workspace, stream=None) -> int:
+    return int(lib().hd_decode_status_bits(_dev_ptr(workspace), _stream_handle(stream)))

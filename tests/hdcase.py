@@ -1,0 +1,69 @@
+"""Test helpers: build a stream with the ORACLE (codebook + encoder), upload it,
+run the library's decode, and compare with the oracle's decode."""
+from __future__ import annotations
+
+import sys
+from dataclasses import dataclass
+
+import numpy as np
+
+import oracle
+
+
+def flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@dataclass
+class Case:
+    x: np.ndarray
+    A: int
+    L: int
+    S: int
+    C: int
+    lengths: np.ndarray
+    codes: np.ndarray
+    enc: oracle.Encoded
+
+    def info(self):
+        from paper_2201_09118_amd import hd
+        e = self.enc
+        return hd.StreamInfo(e.n_symbols, e.n_bits, e.words.size, e.gap.size, e.chunk_counts.size,
+                             self.S, self.C, self.A, self.L)
+
+
+def make_case(x, A, L, S=128, C=32, lengths=None, codes=None) -> Case:
+    x = np.ascontiguousarray(x, dtype=np.uint16)
+    if lengths is None:
+        lengths = oracle.code_lengths(oracle.histogram(x, A), L)
+        codes = oracle.canonical_codes(lengths)
+    enc = oracle.encode(x, lengths, codes, S, C)
+    return Case(x, A, L, S, C, lengths, codes, enc)
+
+
+def upload(case: Case, lut_bits=0, with_gap=True, device="cuda"):
+    import torch
+    from paper_2201_09118_amd import hd
+    tab = hd.Table(case.lengths, case.codes, case.L, lut_bits)
+    e = case.enc
+    w = torch.from_numpy(e.words.view(np.int32)).to(device)
+    g = torch.from_numpy(e.gap).to(device) if with_gap else None
+    c = torch.from_numpy(e.chunk_counts.view(np.int32)).to(device) if with_gap else None
+    return hd.DeviceStream(w, g, c, case.info(), tab)
+
+
+def run_decode(ds, mode=0, tune=None, n_out=None):
+    import torch
+    from paper_2201_09118_amd import hd
+    n = ds.n_symbols if n_out is None else n_out
+    out = torch.full((max(n, 1),), -1, dtype=torch.int16, device="cuda")
+    ws = hd.decode(ds, out, mode, tune)
+    bits = hd.decode_status_bits(ws)
+    torch.cuda.synchronize()
+    return out[:n].cpu().numpy().view(np.uint16), bits
+
+
+def expected(case: Case) -> np.ndarray:
+    e = case.enc
+    return oracle.decode(e.words, e.n_bits, e.n_symbols, case.lengths, case.codes)

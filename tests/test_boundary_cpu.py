@@ -1,0 +1,139 @@
+"""CPU checks of the C-ABI boundary: the library loads, exports everything
+include/hd.h declares, and its host routines (codebook builder, reference
+encoder) agree byte for byte with the oracle.  No GPU work is issued."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import hdsynth
+import oracle
+from conftest import ROOT
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "hd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(hd_[a-z_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2201_09118_amd import hd
+    declared = _header_functions()
+    assert declared, "no declarations parsed"
+    out = subprocess.run(["nm", "-D", "--defined-only", hd.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (hd_[a-z_]+)\b", out))
+    missing = [n for n in declared if n not in exported]
+    assert not missing, missing
+    assert sorted(hd.SIGNATURES) == declared     # the binding covers exactly the header
+    L = ctypes.CDLL(hd.LIB_PATH)
+    for n in declared:
+        assert getattr(L, n) is not None
+
+
+def test_status_strings():
+    from paper_2201_09118_amd import hd
+    for st in range(0, -8, -1):
+        assert hd.status_str(st) and hd.status_str(st) != "unknown status"
+
+
+def _hist_cases():
+    rng = np.random.default_rng(99)
+    cases = []
+    for i in range(25):
+        A = int(rng.choice([2, 5, 64, 256, 1024, 4096]))
+        m = int(rng.integers(1, A + 1))
+        h = np.zeros(A, np.uint64)
+        used = rng.choice(A, m, replace=False)
+        h[used] = (rng.pareto(0.5 + rng.random(), m) * 100).astype(np.uint64) + 1
+        L = int(rng.integers(max(1, int(np.ceil(np.log2(max(m, 2))))), 28))
+        cases.append((h, L))
+    # ties everywhere: equal counts
+    cases.append((np.full(300, 7, np.uint64), 12))
+    cases.append((np.array([5, 5, 5, 5, 1, 1, 1, 1], np.uint64), 3))
+    return cases
+
+
+@pytest.mark.parametrize("idx", range(27))
+def test_build_codebook_matches_oracle_byte_for_byte(idx):
+    from paper_2201_09118_amd import hd
+    h, L = _hist_cases()[idx]
+    ln, cd = hd.build_codebook(h, L)
+    oln = oracle.code_lengths(h, L)
+    ocd = oracle.canonical_codes(oln)
+    assert np.array_equal(ln, oln)
+    assert np.array_equal(cd, ocd)
+
+
+def test_build_codebook_degenerate_and_errors():
+    from paper_2201_09118_amd import hd
+    ln, cd = hd.build_codebook(np.zeros(10, np.uint64), 8)
+    assert ln.sum() == 0
+    h = np.zeros(10, np.uint64)
+    h[3] = 5
+    ln, cd = hd.build_codebook(h, 8)
+    assert ln[3] == 1 and ln.sum() == 1 and cd[3] == 0
+    with pytest.raises(hd.HDError) as ei:
+        hd.build_codebook(np.ones(9, np.uint64), 3)
+    assert ei.value.status == hd.ERR_INFEASIBLE
+    with pytest.raises(hd.HDError):
+        hd.build_codebook(np.ones(9, np.uint64), 33)
+    ln, cd = hd.build_codebook(np.ones(8, np.uint64), 3)
+    assert np.all(ln == 3)
+
+
+@pytest.mark.parametrize("S,C", [(32, 1), (64, 2), (128, 32), (256, 32), (512, 64), (96, 3)])
+def test_encode_ref_matches_oracle(S, C):
+    from paper_2201_09118_amd import hd
+    rng = np.random.default_rng(S + C)
+    x = hdsynth.two_sided_geometric(rng, 200_000, 0.6, 1024)
+    hist = oracle.histogram(x, 1024)
+    ln, cd = hd.build_codebook(hist, 20)
+    hs = hd.encode_ref(x, ln, cd, 20, S, C)
+    e = oracle.encode(x, ln, cd, S, C)
+    assert hs.n_bits == e.n_bits
+    assert np.array_equal(hs.words, e.words)
+    assert np.array_equal(hs.gap, e.gap)
+    assert np.array_equal(hs.chunk_counts, e.chunk_counts)
+    assert hs.info.n_subseq == e.gap.size and hs.info.n_chunks == e.chunk_counts.size
+
+
+def test_encode_ref_edge_cases():
+    from paper_2201_09118_amd import hd
+    ln = np.array([1, 1], np.uint8)
+    cd = np.array([0, 1], np.uint32)
+    hs = hd.encode_ref(np.zeros(0, np.uint16), ln, cd, 4)
+    assert hs.n_bits == 0 and hs.words.size == 2 and hs.gap.size == 0
+    with pytest.raises(hd.HDError) as ei:
+        hd.encode_ref(np.array([0, 2], np.uint16), ln, cd, 4)
+    assert ei.value.status == hd.ERR_SYMBOL
+    for S, C in ((48, 1), (0, 1), (128, 0)):
+        with pytest.raises(hd.HDError) as ei:
+            hd.encode_ref(np.array([0, 1], np.uint16), ln, cd, 4, S, C)
+        assert ei.value.status == hd.ERR_ARG
+    # longest codes (L = 32) and a single used symbol
+    x = np.zeros(1000, np.uint16)
+    h = np.bincount(x, minlength=4).astype(np.uint64)
+    ln1, cd1 = hd.build_codebook(h, 32)
+    e = oracle.encode(x, ln1, cd1, 128, 32)
+    hs = hd.encode_ref(x, ln1, cd1, 32, 128, 32)
+    assert np.array_equal(hs.words, e.words) and np.array_equal(hs.gap, e.gap)
+    fib = [1, 1]
+    while len(fib) < 34:
+        fib.append(fib[-1] + fib[-2])
+    h = np.array(fib, np.uint64)
+    ln2, cd2 = hd.build_codebook(h, 32)
+    assert ln2.max() == 32
+    x = np.repeat(np.arange(34, dtype=np.uint16), 3)
+    rng = np.random.default_rng(5)
+    rng.shuffle(x)
+    e = oracle.encode(x, ln2, cd2, 64, 4)
+    hs = hd.encode_ref(x, ln2, cd2, 32, 64, 4)
+    assert np.array_equal(hs.words, e.words) and np.array_equal(hs.gap, e.gap)
+    assert np.array_equal(hs.chunk_counts, e.chunk_counts)
+    assert np.array_equal(oracle.decode(hs.words, hs.n_bits, x.size, ln2, cd2), x)

@@ -1,0 +1,235 @@
+"""GPU parity: hd_decode through the C-ABI against the CPU oracle.
+
+Inputs (codebook + stream) come from the oracle; the expected output is the
+oracle's bit-serial decode.  Integer work: every comparison is bit-exact."""
+import numpy as np
+import pytest
+
+import hdsynth
+import oracle
+from hdcase import expected, flush, make_case, run_decode, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2201_09118_amd import hd  # noqa: F401  (fails loudly if libhd.so is missing)
+    yield
+
+
+def _check(case, ds=None, mode=0, tune=None, lut_bits=0):
+    ds = ds or upload(case, lut_bits)
+    got, bits = run_decode(ds, mode, tune)
+    want = expected(case)
+    assert np.array_equal(want, case.x)
+    assert bits == 0, f"status bits {bits:#x}"
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError(f"{bad.size} mismatches, first at {bad[:8]}: got {got[bad[:8]]} want {want[bad[:8]]}")
+
+
+def test_config1_gap():
+    flush("config1: n=2^20 A=1024 r=0.35 L=16 S=128 C=32")
+    x = hdsynth.config1_symbols()
+    _check(make_case(x, 1024, 16, 128, 32))
+
+
+def _random_cases():
+    rng = np.random.default_rng(20260)
+    cases = []
+    Ss = [32, 64, 128, 256, 512]
+    Cs = [1, 2, 4, 8, 16, 32, 64]
+    ns = [1, 2, 63, 64, 65, 777, 4096, 54321, 300_001]
+    for i in range(36):
+        S = Ss[i % len(Ss)]
+        C = Cs[(i // 2) % len(Cs)]
+        n = ns[i % len(ns)]
+        A = int(rng.choice([2, 3, 256, 1024, 4096, 65536]))
+        r = float(rng.uniform(0.1, 0.95))
+        L = int(rng.integers(max(1, int(np.ceil(np.log2(min(A, n) + 1)))), 28))
+        lut = int(rng.choice([0, 6, 9, 12, 14]))
+        cases.append((i, S, C, n, A, r, L, lut))
+    return cases
+
+
+@pytest.mark.parametrize("case", _random_cases(), ids=lambda c: f"i{c[0]}-S{c[1]}-C{c[2]}-n{c[3]}-A{c[4]}-L{c[6]}")
+def test_random_streams_gap(case):
+    i, S, C, n, A, r, L, lut = case
+    flush(f"random case {case}")
+    rng = np.random.default_rng(1000 + i)
+    x = hdsynth.two_sided_geometric(rng, n, r, A)
+    used = int((np.bincount(x, minlength=A) > 0).sum())
+    if L < 32 and used > (1 << L):
+        L = int(np.ceil(np.log2(used)))
+    _check(make_case(x, A, L, S, C), lut_bits=lut)
+
+
+def test_all_one_bit_codes_multi_pass_staging():
+    """CR 16: two equiprobable symbols, 128 symbols per 128-bit subsequence,
+    8192 per wavefront tile -- forces several staging passes."""
+    rng = np.random.default_rng(1)
+    x = rng.integers(0, 2, 500_000).astype(np.uint16)
+    case = make_case(x, 2, 8, 128, 32)
+    assert case.lengths.tolist() == [1, 1]
+    ds = upload(case)
+    for stage in (256, 512, 2048, 8192):
+        flush(f"one-bit codes stage={stage}")
+        _check(case, ds, tune={"stage_symbols": stage})
+
+
+def test_all_codes_at_max_length():
+    rng = np.random.default_rng(2)
+    x = rng.integers(0, 4096, 200_000).astype(np.uint16)
+    case = make_case(x, 4096, 12, 128, 32)
+    assert set(case.lengths.tolist()) == {12}
+    _check(case, lut_bits=8)      # every codeword longer than the first level
+    _check(case, lut_bits=12)
+
+
+def test_single_symbol_stream():
+    x = np.full(100_000, 7, np.uint16)
+    _check(make_case(x, 16, 4, 128, 32))
+
+
+def test_fixed_length_code_off_phase():
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 8, 300_000).astype(np.uint16)
+    case = make_case(x, 8, 3, 128, 32)
+    assert set(case.lengths.tolist()) == {3}
+    _check(case)
+
+
+def test_long_codes_limit_binds():
+    """Fibonacci counts: the unconstrained code is 29 deep, so L = 27 binds
+    and many codewords are longer than the first-level table."""
+    fib = [1, 1]
+    while len(fib) < 30:
+        fib.append(fib[-1] + fib[-2])
+    x = np.repeat(np.arange(30, dtype=np.uint16), fib)
+    np.random.default_rng(4).shuffle(x)
+    case = make_case(x, 30, 27, 256, 32)
+    assert case.lengths.max() == 27
+    _check(case, lut_bits=6)
+    _check(case, lut_bits=11)
+
+
+def test_last_subsequence_without_codeword_start():
+    """The final codeword straddles the last subsequence boundary, so the
+    last subsequence owns no codeword (its gap reaches the stream end)."""
+    A = 4
+    lengths = np.array([1, 2, 3, 3], np.uint8)
+    codes = oracle.canonical_codes(lengths)
+    for tail in range(1, 40):
+        x = np.zeros(29 + tail, np.uint16)       # 1-bit codes
+        x[-1] = 3                                # a 3-bit codeword last
+        case = make_case(x, A, 3, 32, 1, lengths, codes)
+        B = case.enc.n_bits
+        if B % 32 in (1, 2):
+            break
+    assert case.enc.chunk_counts[-1] == 0
+    _check(case)
+
+
+@pytest.mark.parametrize("wpg", [4, 8, 16])
+def test_tune_variants(wpg):
+    x = hdsynth.two_sided_geometric(np.random.default_rng(5), 700_000, 0.5, 1024)
+    case = make_case(x, 1024, 24, 128, 32)
+    ds = upload(case)
+    from paper_2201_09118_amd import hd
+    ran = 0
+    for stage in (512, 2048, 4096):
+        for gpc in (0, 1):
+            flush(f"tune wpg={wpg} stage={stage} groups_per_cu={gpc}")
+            try:
+                _check(case, ds, tune={"waves_per_group": wpg, "stage_symbols": stage, "groups_per_cu": gpc})
+                ran += 1
+            except hd.HDError as err:          # LDS request above the per-workgroup limit
+                assert err.status == hd.ERR_UNSUPPORTED
+    assert ran >= 2
+
+
+def test_deterministic_repeat():
+    x = hdsynth.two_sided_geometric(np.random.default_rng(6), 1_000_003, 0.7, 4096)
+    case = make_case(x, 4096, 24, 256, 32)
+    ds = upload(case)
+    a, ba = run_decode(ds)
+    b, bb = run_decode(ds)
+    assert ba == 0 and bb == 0
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, expected(case))
+
+
+def test_empty_stream():
+    import torch
+    from paper_2201_09118_amd import hd
+    case = make_case(np.zeros(0, np.uint16), 4, 2, 128, 32, np.array([1, 1, 0, 0], np.uint8),
+                     np.array([0, 1, 0, 0], np.uint32))
+    ds = upload(case)
+    out = torch.zeros(1, dtype=torch.int16, device="cuda")
+    ws = hd.decode(ds, out)
+    assert hd.decode_status(ws) == hd.OK
+
+
+def test_corrupt_metadata_is_reported():
+    import torch
+    from paper_2201_09118_amd import hd
+    x = hdsynth.two_sided_geometric(np.random.default_rng(8), 100_000, 0.5, 1024)
+    case = make_case(x, 1024, 16, 128, 32)
+    # a chunk count off by one
+    ds = upload(case)
+    ds.chunk_counts[3] += 1
+    _, bits = run_decode(ds, n_out=case.x.size + 64)
+    assert bits & (1 << 3) and bits & (1 << 4)
+    # a gap byte off by one
+    ds = upload(case)
+    ds.gap[10] += 1
+    _, bits = run_decode(ds)
+    assert bits != 0
+    # a symbol count that does not match the stream
+    ds = upload(case)
+    ds.info.n_symbols += 1
+    _, bits = run_decode(ds)
+    assert bits & (1 << 4)
+    # the clean stream still decodes
+    _check(case)
+
+
+def test_argument_errors():
+    import torch
+    from paper_2201_09118_amd import hd
+    x = hdsynth.two_sided_geometric(np.random.default_rng(9), 10_000, 0.5, 256)
+    case = make_case(x, 256, 16, 128, 32)
+    ds = upload(case)
+    out = torch.zeros(x.size + 8, dtype=torch.int16, device="cuda")
+    with pytest.raises(hd.HDError) as ei:
+        hd.decode(ds, out[1:])                       # not 16-byte aligned
+    assert ei.value.status == hd.ERR_ARG
+    need = hd.decode_workspace_size(ds)
+    ws = torch.zeros(need - 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(hd.HDError) as ei:
+        hd.decode(ds, out, workspace=ws)
+    assert ei.value.status == hd.ERR_ARG
+    ds.info.max_len += 1                             # table built for another L
+    with pytest.raises(hd.HDError):
+        hd.decode(ds, out)
+
+
+@pytest.mark.slow
+def test_config2_full_gap():
+    flush("config2: 512^3 Lorenzo codes, A=1024 L=24 S=128 C=32")
+    x = hdsynth.config2_symbols()
+    case = make_case(x, 1024, 24, 128, 32)
+    flush(f"config2 encoded: B={case.enc.n_bits} lbar={case.enc.n_bits / x.size:.3f}")
+    _check(case)
+
+
+@pytest.mark.slow
+def test_config3_full_gap():
+    flush("config3: 280M Gaussian codes, A=4096 L=27 S=256 C=32")
+    x = hdsynth.config3_symbols()
+    case = make_case(x, 4096, 27, 256, 32)
+    flush(f"config3 encoded: B={case.enc.n_bits} lbar={case.enc.n_bits / x.size:.3f}")
+    _check(case)
