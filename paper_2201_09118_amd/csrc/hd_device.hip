@@ -75,10 +75,15 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // ------------------------------------------------------------------------
 //
 // Device image (one allocation):
-//   lut   uint32[2^k1]   entry = symbol | length << 16 for codewords of at
-//                        most k1 bits, indexed by the next k1 stream bits;
-//                        length kLenLong for a prefix of a longer codeword,
-//                        kLenBad for a prefix of no codeword;
+//   lut   uint32[2^k1]   indexed by the next k1 stream bits.  Single format:
+//                        entry = symbol | length << 16 for codewords of at
+//                        most k1 bits; length kLenLong for a prefix of a
+//                        longer codeword, kLenBad for a prefix of no
+//                        codeword.  Pair format (alphabet <= 4096, k1 <= 12):
+//                        entry = sym1 | sym2 << 12 | len1 << 24 | len2 << 28,
+//                        the first codeword and, when it also fits in the k1
+//                        bits, the one after it (len2 = 0: none); len1 = 0
+//                        sends the lookup to the per-length limits;
 //   lim   uint64[33]     lim[l] = first canonical code of length l + number
 //                        of codes of length l: a window whose l-bit prefix is
 //                        below lim[l] (and whose shorter prefixes are not
@@ -90,13 +95,15 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct hd_table {
     void *image = nullptr;
     uint32_t k1 = 0, L = 0, A = 0, n_used = 0;
+    bool pair = false;          // first level holds up to two codewords per entry
     size_t lut_off = 0, lim_off = 0, base_off = 0, syms_off = 0, bytes = 0;
     int device = 0;
 };
 
 namespace {
 
-constexpr uint32_t kDefaultLutBits = 11;
+constexpr uint32_t kDefaultLutBits = 12;      // pair-format tables
+constexpr uint32_t kDefaultLutBitsWide = 11;  // alphabets above 4096
 
 struct TableView {
     const uint32_t *lut;
@@ -142,8 +149,9 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
                 return HD_ERR_UNSUPPORTED;
             n_used += lengths[s] != 0;
         }
-        uint32_t k1 = lut_bits ? lut_bits : kDefaultLutBits;
+        uint32_t k1 = lut_bits ? lut_bits : (A <= 4096 ? kDefaultLutBits : kDefaultLutBitsWide);
         k1 = std::min(k1, L);
+        const bool pair = A <= 4096 && k1 <= 12;
 
         uint64_t bl[33] = {0};
         for (uint32_t s = 0; s < A; ++s)
@@ -180,6 +188,22 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
             for (uint32_t w = lo; w < hi; ++w)
                 lut[w] = s | (l << 16);
         }
+        if (pair) {
+            std::vector<uint32_t> two(nlut, 0);
+            for (uint32_t w = 0; w < nlut; ++w) {
+                const uint32_t e = lut[w], l1 = e >> 16;
+                if (l1 == kLenLong || l1 == kLenBad)
+                    continue;                            // len1 = 0: per-length limits
+                uint32_t v = (e & 0xfffu) | (l1 << 24);
+                if (l1 < k1) {
+                    const uint32_t e2 = lut[(w << l1) & (nlut - 1)], l2 = e2 >> 16;
+                    if (l2 != kLenLong && l2 != kLenBad && l2 <= k1 - l1)
+                        v |= ((e2 & 0xfffu) << 12) | (l2 << 28);
+                }
+                two[w] = v;
+            }
+            lut.swap(two);
+        }
         std::vector<uint64_t> lim(33, 0);
         std::vector<int64_t> base(33, 0);
         for (uint32_t l = 1; l <= 32; ++l) {
@@ -194,6 +218,7 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
         t->L = L;
         t->A = A;
         t->n_used = n_used;
+        t->pair = pair;
         t->lut_off = 0;
         t->lim_off = align_up(size_t(4) * nlut, 16);
         t->base_off = t->lim_off + 33 * 8;
@@ -279,18 +304,20 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 32 stream bits starting at relative bit r, from the LDS copy T of the
-// tile's units where T[i] holds unit (first unit of the tile) - 1 + i.
-// With q = r + 31, the bits sit in the unit pair (T[q>>5], T[q>>5 + 1])
-// shifted right by (-r) mod 32 = (~q) mod 32.
-__device__ __forceinline__ uint32_t window_at(const uint32_t *T, uint32_t q)
+// 32 stream bits of one lane from the wavefront's transposed copy TT of its
+// units: unit w of lane l sits at TT[w * 64 + l], with w = 0 a don't-care
+// slot, w = 1 .. S/32 the lane's own subsequence and w = S/32 + 1 the first
+// unit of the next subsequence.  For a bit r of the subsequence, q = r + 31
+// selects the unit pair (q >> 5, q >> 5 + 1) -- one ds_read2st64, all 64
+// lanes on distinct banks -- and the right shift (-r) mod 32 = (~q) mod 32.
+__device__ __forceinline__ uint32_t window_at(const uint32_t *TTl, uint32_t q)
 {
-    const uint32_t i = q >> 5;
-    return __builtin_amdgcn_alignbit(T[i], T[i + 1], ~q);
+    const uint32_t *p = TTl + ((q >> 5) << 6);
+    return __builtin_amdgcn_alignbit(p[0], p[64], ~q);
 }
 
 // Codewords longer than the first level: canonical per-length limits.
-__device__ __noinline__ uint32_t decode_long(uint32_t v, uint32_t k1, uint32_t L,
+__device__ __forceinline__ uint32_t decode_long(uint32_t v, uint32_t k1, uint32_t L,
                                              const uint64_t *lim, const int64_t *base,
                                              const uint16_t *syms, uint32_t *len_out)
 {
@@ -335,25 +362,42 @@ __device__ __forceinline__ void load_table(const SmemTable &t, const TableView &
     }
 }
 
-// One codeword at relative bit position q - 31.  Returns the symbol and
-// advances q by the codeword length; an invalid window advances by one bit
-// and raises kErrBadCode (so every loop still terminates).
-__device__ __forceinline__ uint32_t decode_one(const uint32_t *T, uint32_t &q, const SmemTable &st,
-                                               const TableView &g, uint32_t sh, uint32_t &err)
+// First-level lookup at relative position q - 31: up to two codewords.  A
+// codeword longer than the first level (or a window matching no codeword)
+// goes through the per-length limits; an invalid window reports kErrBadCode
+// and consumes one bit so every loop still ends.  In the pair format a valid
+// entry has len1 >= 1, so `entry < 2^24` alone flags the slow case.
+template <bool PAIR>
+__device__ __forceinline__ void lookup(const uint32_t *TTl, uint32_t q, const SmemTable &st,
+                                       const TableView &g, uint32_t sh, uint32_t &s1,
+                                       uint32_t &s2, uint32_t &l1, uint32_t &l2, uint32_t &err)
 {
-    const uint32_t v = window_at(T, q);
+    const uint32_t v = window_at(TTl, q);
     const uint32_t e = st.lut[v >> sh];
-    uint32_t len = e >> 16;
-    uint32_t sym = e & 0xffffu;
-    if (len - 1u >= g.k1) {   // kLenLong (0) or kLenBad (63)
-        sym = decode_long(v, g.k1, g.L, st.lim, st.base, g.syms, &len);
-        if (len == 0) {
-            err |= kErrBadCode;
-            len = 1;
+    bool slow;
+    if (PAIR) {
+        s1 = e & 0xfffu;
+        s2 = (e >> 12) & 0xfffu;
+        l1 = (e >> 24) & 0xfu;
+        l2 = e >> 28;
+        slow = e < (1u << 24);
+    } else {
+        s1 = e & 0xffffu;
+        s2 = 0;
+        l1 = e >> 16;
+        l2 = 0;
+        slow = l1 - 1u >= g.k1;
+    }
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(slow) != 0, 0)) {
+        if (slow) {
+            s1 = decode_long(v, g.k1, g.L, st.lim, st.base, g.syms, &l1);
+            l2 = 0;
+            if (l1 == 0) {
+                err |= kErrBadCode;
+                l1 = 1;
+            }
         }
     }
-    q += len;
-    return sym;
 }
 
 // ------------------------------------------------------------------------
@@ -446,6 +490,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_finish(const uint32_t *__
 // Gap-mode decode (persistent, one lane per subsequence)
 // ------------------------------------------------------------------------
 
+constexpr uint32_t kMaxUnitsPerLane = 16;   // subsequences of at most 512 bits
+
 struct GapArgs {
     const uint32_t *words;
     const uint8_t *gap;
@@ -453,24 +499,24 @@ struct GapArgs {
     uint16_t *out;
     uint32_t *status;
     TableView tab;
-    uint64_t n, B, K, n_words;
+    uint64_t n, B, K, M, n_words;
     uint32_t S, C, stage;        // stage: staging symbols per wave (multiple of 64)
 };
 
-// LDS of one wave's private area: the unit copy T[0 .. 2S + 2) placed at
-// word 3 so that T + 1 is 16-byte aligned (2S + 8 words, a multiple of 16
-// bytes), then the staging tile.
+// LDS of one wave's private area: the transposed unit copy TT (S/32 + 2
+// words per lane, 64 lanes) and the staging tile.
 __host__ __device__ __forceinline__ uint32_t wave_units_bytes(uint32_t S)
 {
-    return (2 * S + 8) * 4;
+    return ((S >> 5) + 2) * 64 * 4;
 }
 
+// ... plus 64 dummy uint16 slots that absorb untaken second-symbol stores.
 __host__ __device__ __forceinline__ uint32_t wave_area_bytes(uint32_t S, uint32_t stage)
 {
-    return wave_units_bytes(S) + 2 * stage;
+    return wave_units_bytes(S) + 2 * stage + 128;
 }
 
-template <int WPG>
+template <int WPG, bool PAIR>
 __global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -484,85 +530,119 @@ __global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
     const uint32_t S = a.S;
     const uint32_t wps = S >> 5;
     unsigned char *area = smem + table_lds_bytes(g.k1) + wv * wave_area_bytes(S, a.stage);
-    uint32_t *T = reinterpret_cast<uint32_t *>(area) + 3;
+    uint32_t *TTl = reinterpret_cast<uint32_t *>(area) + lane;
     uint16_t *stage = reinterpret_cast<uint16_t *>(area + wave_units_bytes(S));
+    uint16_t *dummy = stage + a.stage + lane;
     const uint32_t sh = 32 - g.k1;
-    const uint32_t nT = 2 * S + 2;
     const uint32_t PB = a.stage - 8;
 
     uint32_t err = 0;
     const uint64_t ntiles = (a.K + 63) >> 6;
-    for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv; t < ntiles;
-         t += static_cast<uint64_t>(gridDim.x) * WPG) {
-        const uint64_t k0 = t << 6;
-        const uint64_t w0 = k0 * wps;                 // first unit of the tile
-        // 1. units [w0 - 1, w0 + 2S + 1) -> T[0 .. 2S + 2)
-        {
-            const uint64_t nfull = 2 * S;              // units w0 .. w0 + 2S
-            if (w0 + nfull <= a.n_words) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(a.words + w0);
-                uint4 *dst = reinterpret_cast<uint4 *>(T + 1);
-                for (uint32_t i = lane; i < nfull / 4; i += 64)
-                    dst[i] = src[i];
-            } else {
-                for (uint32_t i = lane; i < nfull; i += 64)
-                    T[1 + i] = (w0 + i < a.n_words) ? a.words[w0 + i] : 0u;
-            }
-            if (lane == 0)
-                T[0] = w0 ? a.words[w0 - 1] : 0u;
-            if (lane == 1)
-                T[nT - 1] = (w0 + nfull < a.n_words) ? a.words[w0 + nfull] : 0u;
-        }
-        wave_lds_sync();
+    const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * WPG;
 
-        // 2. count pass
+    // Tile inputs travel through registers one tile ahead: while tile t is
+    // decoded, the units, gap bytes and chunk offsets of the wavefront's next
+    // tile are already in flight.
+    uint32_t pw[kMaxUnitsPerLane];
+    uint32_t pwn = 0, pgk = 0, pgn = 0;
+    uint64_t pco_lo = 0, pco_hi = 0;
+    auto prefetch = [&](uint64_t tt) {
+        const uint64_t k = (tt << 6) + lane;
+        if (tt < ntiles && k < a.K) {
+            const uint32_t *src = a.words + k * wps;
+            if ((wps & 3) == 0) {
+#pragma unroll
+                for (uint32_t i = 0; i < kMaxUnitsPerLane / 4; ++i)
+                    if (4 * i < wps) {
+                        const uint4 v = *reinterpret_cast<const uint4 *>(src + 4 * i);
+                        pw[4 * i] = v.x;
+                        pw[4 * i + 1] = v.y;
+                        pw[4 * i + 2] = v.z;
+                        pw[4 * i + 3] = v.w;
+                    }
+            } else {
+#pragma unroll
+                for (uint32_t i = 0; i < kMaxUnitsPerLane; ++i)
+                    if (i < wps)
+                        pw[i] = src[i];
+            }
+            pwn = src[wps];                          // (k+1)*S/32 < n_words for k < K
+            pgk = a.gap[k];
+            pgn = k + 1 < a.K ? a.gap[k + 1] : 0u;
+            pco_lo = a.chunk_off[k / a.C];            // bounds of this lane's chunk
+            pco_hi = a.chunk_off[k / a.C + 1];        // (k / C + 1 <= M for k < K)
+        }
+    };
+    uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv;
+    prefetch(t);
+    for (; t < ntiles; t += tstride) {
+        const uint64_t k0 = t << 6;
         const uint64_t k = k0 + lane;
         const bool act = k < a.K;
-        const uint64_t bit0 = k0 * S;
-        uint32_t gk = act ? a.gap[k] : 0u;
-        uint32_t rs = lane * S + gk;
+        // 1. the prefetched units go to this lane's column of TT
+        if (act) {
+#pragma unroll
+            for (uint32_t i = 0; i < kMaxUnitsPerLane; ++i)
+                if (i < wps)
+                    TTl[(i + 1) * 64] = pw[i];
+            TTl[(wps + 1) * 64] = pwn;
+        }
+        const uint32_t gk = act ? pgk : 0u;
+        const uint32_t gn = pgn;
+        const uint64_t c_lo = pco_lo, c_hi = pco_hi;
+        prefetch(t + tstride);
+        wave_lds_sync();
+
+        // 2. count pass (positions relative to the lane's subsequence start)
         uint32_t re = 0;
         if (act) {
             const uint64_t e = (k + 1) * S < a.B ? (k + 1) * S : a.B;
-            re = static_cast<uint32_t>(e - bit0);
+            re = static_cast<uint32_t>(e - k * S);
         }
+        uint32_t rs = gk;
         if (gk >= 32) {
             err |= kErrGapRange;
             rs = re;
         }
         if (rs > re)
             rs = re;
-        uint32_t q = rs + 31;
         const uint32_t qe = re + 31;
         uint32_t cnt = 0;
-        while (q < qe) {
-            decode_one(T, q, st, g, sh, err);
-            ++cnt;
-        }
-        // the walk must stop exactly on the next subsequence's start
+        uint32_t q = rs + 31;
         {
-            uint32_t gn = __shfl_down(gk, 1, 64);
-            if (lane == 63)
-                gn = (k + 1 < a.K) ? a.gap[k + 1] : 0u;
-            if (act) {
-                const uint64_t expect = (k + 1 < a.K) ? (uint64_t)(lane + 1) * S + gn : a.B - bit0;
-                if ((uint64_t)(q - 31) != expect)
-                    err |= kErrLaneEnd;
+            // both codewords of a pair are taken; a second codeword that
+            // starts at or past the end is given back after the loop
+            uint32_t qm = q, l2 = 0;
+            while (q < qe) {
+                uint32_t s1, s2, l1;
+                lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
+                qm = q + l1;
+                q = qm + l2;
+                cnt += 1 + (l2 != 0);
+            }
+            if (PAIR && l2 != 0 && qm >= qe) {
+                --cnt;
+                q = qm;
             }
         }
+        // the walk must stop exactly on the next subsequence's start
+        if (act) {
+            const uint32_t expect = (k + 1 < a.K) ? S + gn : re;
+            if (q - 31 != expect)
+                err |= kErrLaneEnd;
+        }
 
-        // 3. output indices
+        // 3. output indices: wavefront scan inside the tile; the tile starts
+        //    at the output offset of its first chunk (lane 0's chunk)
         const uint32_t incl = wave_incl_scan(cnt, lane);
         const uint32_t excl = incl - cnt;
         const uint32_t total = __shfl(incl, 63, 64);
-        const uint64_t gbase = a.chunk_off[k0 / a.C];
+        const uint64_t gbase = __shfl(c_lo, 0, 64);
         {
             const uint32_t cl = lane % a.C;
             const uint32_t excl_first = __shfl(excl, lane - cl, 64);
             if (act && (cl == a.C - 1 || k == a.K - 1)) {
-                const uint64_t c = k / a.C;
-                if (gbase + excl_first != a.chunk_off[c] ||
-                    gbase + incl != a.chunk_off[c + 1])
+                if (gbase + excl_first != c_lo || gbase + incl != c_hi)
                     err |= kErrChunkSum;
             }
         }
@@ -577,9 +657,19 @@ __global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
             // dst index of symbol j: a0 + excl + j - pb (>= a0 whenever j < jmax)
             uint16_t *dst = stage + (static_cast<int32_t>(a0 + excl) - static_cast<int32_t>(pb));
             while (j < jmax) {
-                const uint32_t s = decode_one(T, q, st, g, sh, err);
-                dst[j] = static_cast<uint16_t>(s);
+                uint32_t s1, s2, l1, l2;
+                lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
+                dst[j] = static_cast<uint16_t>(s1);
                 ++j;
+                if (PAIR) {
+                    // second codeword: stored when it is this lane's and in
+                    // this pass, else written to the lane's dummy slot
+                    const bool two = l2 != 0 && j < jmax;
+                    *(two ? dst + j : dummy) = static_cast<uint16_t>(s2);
+                    j += two;
+                    l1 += two ? l2 : 0u;
+                }
+                q += l1;
             }
             wave_lds_sync();
             uint64_t g0 = gbase + pb;
@@ -632,8 +722,10 @@ hd_status check_stream(const hd_dstream *s, hd_mode m)
         return HD_ERR_ARG;
     const hd_stream_info &i = s->info;
     const hd_table *t = s->table;
-    if (i.subseq_bits < 32 || i.subseq_bits % 32 != 0 || i.subseq_bits > 4096)
-        return i.subseq_bits % 32 ? HD_ERR_ARG : HD_ERR_UNSUPPORTED;
+    if (i.subseq_bits < 32 || i.subseq_bits % 32 != 0)
+        return HD_ERR_ARG;
+    if (i.subseq_bits > 32 * kMaxUnitsPerLane)
+        return HD_ERR_UNSUPPORTED;
     if (i.chunk_subseqs == 0)
         return HD_ERR_ARG;
     if (i.alphabet_size != t->A || i.max_len != t->L)
@@ -663,8 +755,16 @@ hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
     const DeviceInfo *dev = device_info();
     if (!dev)
         return HD_ERR_DEVICE;
-    p->wpg = tune && tune->waves_per_group ? tune->waves_per_group : 8;
-    p->stage = tune && tune->stage_symbols ? tune->stage_symbols : 2048;
+    // Default staging: a wavefront tile of 64 subsequences decodes about
+    // 64 * S / (mean code length) symbols; a quarter of headroom keeps nearly
+    // every tile to one staging pass.
+    const hd_stream_info &si = s->info;
+    const double per_tile = si.n_bits ? 64.0 * si.subseq_bits * double(si.n_symbols) / double(si.n_bits)
+                                      : 1024.0;
+    uint32_t auto_stage = static_cast<uint32_t>(per_tile * 1.25) + 64;
+    auto_stage = std::min<uint32_t>(8192, std::max<uint32_t>(512, (auto_stage + 255) / 256 * 256));
+    p->wpg = tune && tune->waves_per_group ? tune->waves_per_group : 4;
+    p->stage = tune && tune->stage_symbols ? tune->stage_symbols : auto_stage;
     if (p->wpg != 4 && p->wpg != 8 && p->wpg != 16)
         return HD_ERR_ARG;
     if (p->stage < 256 || p->stage > 16384 || p->stage % 64)
@@ -689,18 +789,18 @@ size_t gap_ws_bytes(uint64_t M)
     return kWsHeader + align_up(8 * (M + 1), 256) + align_up(8 * nblk, 256);
 }
 
-template <int WPG>
+template <int WPG, bool PAIR>
 hd_status launch_gap(const GapArgs &a, const Plan &p, hipStream_t stream)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_gap<WPG>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_gap<WPG, PAIR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 static_cast<int>(device_info()->lds_per_block)) != hipSuccess)
             return HD_ERR_DEVICE;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_decode_gap<WPG>, dim3(p.grid), dim3(WPG * 64), p.lds_bytes, stream, a);
+    hipLaunchKernelGGL((k_decode_gap<WPG, PAIR>), dim3(p.grid), dim3(WPG * 64), p.lds_bytes, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
 
@@ -816,14 +916,22 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     a.n = i.n_symbols;
     a.B = i.n_bits;
     a.K = i.n_subseq;
+    a.M = i.n_chunks;
     a.n_words = i.n_words;
     a.S = i.subseq_bits;
     a.C = i.chunk_subseqs;
     a.stage = p.stage;
+    if (s->table->pair) {
+        switch (p.wpg) {
+        case 4: return launch_gap<4, true>(a, p, stream);
+        case 8: return launch_gap<8, true>(a, p, stream);
+        default: return launch_gap<16, true>(a, p, stream);
+        }
+    }
     switch (p.wpg) {
-    case 4: return launch_gap<4>(a, p, stream);
-    case 8: return launch_gap<8>(a, p, stream);
-    default: return launch_gap<16>(a, p, stream);
+    case 4: return launch_gap<4, false>(a, p, stream);
+    case 8: return launch_gap<8, false>(a, p, stream);
+    default: return launch_gap<16, false>(a, p, stream);
     }
 }
 
