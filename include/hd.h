@@ -208,6 +208,18 @@ hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_
                         void *workspace, size_t ws_bytes, void *hip_stream);
 
 /*
+ * After hd_decode_prepare (or hd_decode) in HD_MODE_SELF_SYNC on this
+ * workspace: copies the synchronization point found for every subsequence,
+ * relative to the subsequence start (the gap-array convention), into
+ * gap_out[0 .. n_subseq) (device memory), asynchronously on hip_stream.  The
+ * gap array holds exactly what self-synchronization finds (Sec. III-C), so a
+ * plain Huffman stream can be synchronized once and decoded in HD_MODE_GAP
+ * afterwards.  HD_ERR_ARG for a workspace smaller than the self-sync size.
+ */
+hd_status hd_decode_sync_points(const hd_dstream *s, const void *workspace, size_t ws_bytes,
+                                uint8_t *gap_out, void *hip_stream);
+
+/*
  * Workspace bytes for hd_decode_batch over n_streams streams.
  */
 hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, uint32_t n_streams,

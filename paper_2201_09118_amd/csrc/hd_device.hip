@@ -700,6 +700,269 @@ __global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
         atomicOr(a.status, err);
 }
 
+// ------------------------------------------------------------------------
+// Self-synchronization (Sec. III-B-2, steps 1 and 2)
+// ------------------------------------------------------------------------
+//
+// A tile is 64 consecutive subsequences, one per lane of a wavefront.  Every
+// lane keeps a path (start, exit, count): the codewords decoded from its
+// start up to its exit, the first codeword start at or after the end of its
+// subsequence.  Decoding from a bit position is a deterministic walk, so two
+// paths that reach one position coincide from there on; comparing positions
+// is therefore an exact test of "meeting up".
+//
+// Step 1 (intra-tile): every lane first decodes from its raw boundary (lane
+// 0 from the tile's entry).  Then, in rounds, each lane takes its
+// predecessor's exit as its start; a lane whose start changed walks the new
+// path in lockstep with the old one until they meet (the exit stays, the
+// count is re-derived) or the new path leaves the subsequence (a new exit).
+// Rounds end when a wavefront ballot finds no exit changed; after round r
+// lanes 0..r agree with the entry, so at most 64 rounds run, and no budget
+// ever decides the result.
+//
+// Step 2 (inter-tile): the entry of tile u is the exit of tile u-1's last
+// lane.  Phase 1 assumes entry 0 and then walks lane 0's subsequence from
+// every entry g < L; if all of them leave at the same exit, the tile is
+// entry-independent: only lane 0's start and count depend on the true entry
+// (the count per entry is recorded).  The link kernel fixes lane 0 of every
+// tile whose predecessor's exit is final, and re-syncs, in order, runs of
+// entry-dependent tiles (codes that never resynchronize end up here).
+
+constexpr uint32_t kSyncRecBytes = 72;
+
+struct SyncRec {
+    uint8_t last_entry;       // next tile's lane-0 start implied by this tile's path
+    uint8_t indep;            // lane 0's exit is the same for every entry < L
+    uint8_t pad[6];
+    uint16_t count_at[32];    // lane 0's codeword count from entry g
+};
+static_assert(sizeof(SyncRec) == kSyncRecBytes, "record layout");
+
+struct SyncArgs {
+    const uint32_t *words;
+    uint8_t *gap_s;           // [K] sync point of every subsequence (relative)
+    uint32_t *tot;            // [ntiles] codewords per tile
+    SyncRec *rec;             // [ntiles]
+    uint32_t *status;
+    TableView tab;
+    uint64_t B, K, ntiles, n_words;
+    uint32_t S;
+};
+
+template <bool PAIR>
+__device__ __forceinline__ uint32_t codeword_len(const uint32_t *TTc, uint32_t r, const SmemTable &st,
+                                                 const TableView &g, uint32_t sh)
+{
+    uint32_t s1, s2, l1, l2, e = 0;
+    lookup<PAIR>(TTc, r + 31, st, g, sh, s1, s2, l1, l2, e);
+    return l1;
+}
+
+// Path from relative bit r: codewords starting before E, and the first start
+// at or after E (exit).
+template <bool PAIR>
+__device__ __forceinline__ void run_path(const uint32_t *TTc, uint32_t r, uint32_t E, const SmemTable &st,
+                                         const TableView &g, uint32_t sh, uint32_t &exit, uint32_t &cnt)
+{
+    uint32_t q = r + 31, qm = q, l2 = 0, e = 0;
+    const uint32_t qe = E + 31;
+    cnt = 0;
+    while (q < qe) {
+        uint32_t s1, s2, l1;
+        lookup<PAIR>(TTc, q, st, g, sh, s1, s2, l1, l2, e);
+        qm = q + l1;
+        q = qm + l2;
+        cnt += 1 + (l2 != 0);
+    }
+    if (PAIR && l2 != 0 && qm >= qe) {
+        --cnt;
+        q = qm;
+    }
+    exit = q - 31;
+}
+
+// New path from `in` against the old path (st0, ex0, cn0): advance whichever
+// position is behind until they meet or the new one reaches E.
+template <bool PAIR>
+__device__ __forceinline__ void walk_merge(const uint32_t *TTc, uint32_t in, uint32_t st0, uint32_t ex0,
+                                           uint32_t cn0, uint32_t E, const SmemTable &st,
+                                           const TableView &g, uint32_t sh, uint32_t &ex, uint32_t &cn)
+{
+    uint32_t a = in, b = st0, na = 0, nb = 0;
+    for (;;) {
+        if (a == b) {
+            ex = ex0;
+            cn = a >= E ? na : na + cn0 - nb;
+            return;
+        }
+        if (a >= E) {
+            ex = a;
+            cn = na;
+            return;
+        }
+        const uint32_t len = codeword_len<PAIR>(TTc, min(a, b), st, g, sh);
+        if (a < b) {
+            a += len;
+            ++na;
+        } else {
+            b += len;
+            ++nb;
+        }
+    }
+}
+
+// Loads the tile's units into the lane columns of TT (see window_at).
+__device__ __forceinline__ void load_units(uint32_t *TTl, const uint32_t *words, uint64_t k, uint64_t K,
+                                           uint32_t wps)
+{
+    if (k < K) {
+        const uint32_t *src = words + k * wps;
+        for (uint32_t w = 0; w < wps; ++w)
+            TTl[(w + 1) * 64] = src[w];
+        TTl[(wps + 1) * 64] = src[wps];
+    }
+}
+
+// Step 1 for one tile with lane 0 starting at e0.
+template <bool PAIR>
+__device__ void sync_tile(const uint32_t *TTl, int lane, bool act, uint32_t E, uint32_t S, uint32_t e0,
+                          const SmemTable &st, const TableView &g, uint32_t sh, uint32_t &start,
+                          uint32_t &exit, uint32_t &cnt)
+{
+    start = lane == 0 ? e0 : 0u;
+    exit = start;
+    cnt = 0;
+    if (act)
+        run_path<PAIR>(TTl, start, E, st, g, sh, exit, cnt);
+    for (uint32_t round = 0; round <= 64; ++round) {
+        uint32_t in = __shfl_up(exit, 1, 64) - S;
+        if (lane == 0)
+            in = e0;
+        bool changed = false;
+        if (act && in != start) {
+            uint32_t ex, cn;
+            walk_merge<PAIR>(TTl, in, start, exit, cnt, E, st, g, sh, ex, cn);
+            changed = ex != exit;
+            start = in;
+            exit = ex;
+            cnt = cn;
+        }
+        if (__builtin_amdgcn_ballot_w64(changed) == 0)
+            break;
+    }
+}
+
+// Per-lane subsequence end: S, or the stream end for the last subsequence.
+__device__ __forceinline__ uint32_t lane_end(uint64_t k, uint64_t K, uint64_t B, uint32_t S)
+{
+    if (k >= K)
+        return 0;
+    return k + 1 == K ? static_cast<uint32_t>(B - k * S) : S;
+}
+
+// Runs step 1 on tile t, stores its sync points and codeword total, and
+// returns the next tile's entry implied by the tile's last exit.
+template <bool PAIR>
+__device__ uint32_t sync_and_store(const SyncArgs &a, uint64_t t, uint32_t *TTl, int lane, uint32_t e0,
+                                   bool with_record, const SmemTable &st, const TableView &g, uint32_t sh)
+{
+    const uint32_t S = a.S;
+    const uint64_t k = (t << 6) + lane;
+    const bool act = k < a.K;
+    const uint32_t E = lane_end(k, a.K, a.B, S);
+    uint32_t start, exit, cnt;
+    sync_tile<PAIR>(TTl, lane, act, E, S, e0, st, g, sh, start, exit, cnt);
+    if (act)
+        a.gap_s[k] = static_cast<uint8_t>(start);
+    const uint32_t total = static_cast<uint32_t>(wave_sum_u64(cnt));
+    const uint32_t last_exit = __shfl(exit, 63, 64);
+    if (with_record) {
+        // entry independence of lane 0: walk its subsequence from every entry
+        const uint32_t *TT0 = TTl - lane;
+        const uint32_t st0 = __shfl(start, 0, 64), ex0 = __shfl(exit, 0, 64);
+        const uint32_t cn0 = __shfl(cnt, 0, 64), E0 = __shfl(E, 0, 64);
+        uint32_t exg = ex0, cng = cn0;
+        const bool probe = lane < static_cast<int>(g.L);
+        if (probe && static_cast<uint32_t>(lane) != st0)
+            walk_merge<PAIR>(TT0, lane, st0, ex0, cn0, E0, st, g, sh, exg, cng);
+        const bool differs = probe && exg != ex0;
+        const bool indep = __builtin_amdgcn_ballot_w64(differs) == 0;
+        SyncRec *r = a.rec + t;
+        if (lane < 32)
+            r->count_at[lane] = static_cast<uint16_t>(probe ? cng : 0u);
+        if (lane == 0) {
+            r->last_entry = static_cast<uint8_t>(last_exit - S);
+            r->indep = indep ? 1 : 0;
+            a.tot[t] = total;
+        }
+    } else if (lane == 0) {
+        a.tot[t] = total;
+        a.rec[t].last_entry = static_cast<uint8_t>(last_exit - S);
+    }
+    return last_exit - S;
+}
+
+template <int WPG, bool PAIR>
+__global__ __launch_bounds__(WPG * 64) void k_ss_sync(SyncArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const TableView &g = a.tab;
+    const SmemTable st = carve_table(smem, g.k1);
+    load_table(st, g);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *a.status = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const uint32_t wps = a.S >> 5;
+    uint32_t *TTl = reinterpret_cast<uint32_t *>(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S)) + lane;
+    const uint32_t sh = 32 - g.k1;
+    for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv; t < a.ntiles;
+         t += static_cast<uint64_t>(gridDim.x) * WPG) {
+        load_units(TTl, a.words, (t << 6) + lane, a.K, wps);
+        wave_lds_sync();
+        sync_and_store<PAIR>(a, t, TTl, lane, 0u, true, st, g, sh);
+        wave_lds_sync();
+    }
+}
+
+template <int WPG, bool PAIR>
+__global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const TableView &g = a.tab;
+    const SmemTable st = carve_table(smem, g.k1);
+    load_table(st, g);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const uint32_t wps = a.S >> 5;
+    uint32_t *TTl = reinterpret_cast<uint32_t *>(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S)) + lane;
+    const uint32_t sh = 32 - g.k1;
+    for (uint64_t u = static_cast<uint64_t>(blockIdx.x) * WPG + wv + 1; u < a.ntiles;
+         u += static_cast<uint64_t>(gridDim.x) * WPG) {
+        // tile 0 starts at the true stream start; an entry-independent
+        // tile's last exit does not depend on its own entry
+        const bool prev_final = u == 1 || a.rec[u - 1].indep;
+        if (!prev_final)
+            continue;                       // part of a run re-synced below
+        uint32_t e = a.rec[u - 1].last_entry;
+        for (uint64_t v = u; v < a.ntiles; ++v) {
+            if (a.rec[v].indep) {
+                if (lane == 0) {
+                    a.gap_s[v << 6] = static_cast<uint8_t>(e);
+                    a.tot[v] = a.tot[v] + a.rec[v].count_at[e] - a.rec[v].count_at[0];
+                }
+                break;
+            }
+            load_units(TTl, a.words, (v << 6) + lane, a.K, wps);
+            wave_lds_sync();
+            e = sync_and_store<PAIR>(a, v, TTl, lane, e, false, st, g, sh);
+            wave_lds_sync();
+        }
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------
@@ -789,6 +1052,83 @@ size_t gap_ws_bytes(uint64_t M)
     return kWsHeader + align_up(8 * (M + 1), 256) + align_up(8 * nblk, 256);
 }
 
+// Self-sync workspace: the gap-mode part sized for one chunk per tile, then
+// the found sync points, per-tile totals and per-tile records.
+struct SyncWs {
+    uint8_t *gap_s;
+    uint32_t *tot;
+    SyncRec *rec;
+};
+
+size_t sync_ws_bytes(uint64_t K)
+{
+    const uint64_t nt = ceil_div(K, 64);
+    return gap_ws_bytes(nt) + align_up(K, 256) + align_up(4 * nt, 256) + align_up(kSyncRecBytes * nt, 256);
+}
+
+SyncWs sync_ws(void *workspace, uint64_t K)
+{
+    const uint64_t nt = ceil_div(K, 64);
+    char *p = static_cast<char *>(workspace) + gap_ws_bytes(nt);
+    SyncWs w;
+    w.gap_s = reinterpret_cast<uint8_t *>(p);
+    p += align_up(K, 256);
+    w.tot = reinterpret_cast<uint32_t *>(p);
+    p += align_up(4 * nt, 256);
+    w.rec = reinterpret_cast<SyncRec *>(p);
+    return w;
+}
+
+template <int WPG, bool PAIR>
+hd_status launch_sync(const SyncArgs &a, uint32_t grid, uint32_t lds, hipStream_t stream)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        const int lim = static_cast<int>(device_info()->lds_per_block);
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_sync<WPG, PAIR>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_link<WPG, PAIR>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
+            return HD_ERR_DEVICE;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_ss_sync<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
+    hipLaunchKernelGGL((k_ss_link<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
+    return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
+}
+
+// Enqueues steps 1-2 of self-synchronization: sync points into gap_s and
+// per-tile codeword totals into tot.
+hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, hipStream_t stream)
+{
+    const DeviceInfo *dev = device_info();
+    if (!dev)
+        return HD_ERR_DEVICE;
+    const hd_stream_info &i = s->info;
+    constexpr int kWpg = 8;
+    const uint32_t lds = table_lds_bytes(s->table->k1) + kWpg * wave_units_bytes(i.subseq_bits);
+    if (lds > dev->lds_per_block)
+        return HD_ERR_UNSUPPORTED;
+    const uint32_t fit = std::max<uint32_t>(1, std::min<uint32_t>(static_cast<uint32_t>(dev->lds_per_cu / lds), 32 / kWpg));
+    const uint64_t nt = ceil_div(i.n_subseq, 64);
+    const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nt, kWpg),
+                                                                                      uint64_t(dev->cus) * fit)));
+    SyncArgs a;
+    a.words = s->words;
+    a.gap_s = w.gap_s;
+    a.tot = w.tot;
+    a.rec = w.rec;
+    a.status = status;
+    a.tab = view_of(s->table);
+    a.B = i.n_bits;
+    a.K = i.n_subseq;
+    a.ntiles = nt;
+    a.n_words = i.n_words;
+    a.S = i.subseq_bits;
+    return s->table->pair ? launch_sync<kWpg, true>(a, grid, lds, stream)
+                          : launch_sync<kWpg, false>(a, grid, lds, stream);
+}
+
 template <int WPG, bool PAIR>
 hd_status launch_gap(const GapArgs &a, const Plan &p, hipStream_t stream)
 {
@@ -829,11 +1169,8 @@ extern "C" hd_status hd_decode_workspace_size(const hd_dstream *s, hd_mode m, co
     hd_status st = check_stream(s, m);
     if (st != HD_OK)
         return st;
-    if (m == HD_MODE_GAP) {
-        *bytes = gap_ws_bytes(s->info.n_chunks);
-        return HD_OK;
-    }
-    return HD_ERR_UNSUPPORTED;
+    *bytes = m == HD_MODE_GAP ? gap_ws_bytes(s->info.n_chunks) : sync_ws_bytes(s->info.n_subseq);
+    return HD_OK;
 }
 
 namespace {
@@ -878,13 +1215,24 @@ extern "C" hd_status hd_decode_prepare(const hd_dstream *s, hd_mode m, const hd_
     hd_status st = check_call(s, m, tune, workspace, ws_bytes);
     if (st != HD_OK)
         return st;
-    if (m != HD_MODE_GAP)
-        return HD_ERR_UNSUPPORTED;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const hd_stream_info &i = s->info;
-    const WsView w = ws_view(workspace, i.n_chunks);
-    return enqueue_chunk_scan(s->chunk_counts, i.n_chunks, i.n_symbols, w.off, w.partial, w.status,
-                              stream);
+    if (m == HD_MODE_GAP) {
+        const WsView w = ws_view(workspace, i.n_chunks);
+        return enqueue_chunk_scan(s->chunk_counts, i.n_chunks, i.n_symbols, w.off, w.partial, w.status,
+                                  stream);
+    }
+    // self-sync: steps 1-2 find the sync points and tile totals, step 3 scans
+    // the totals (one chunk per tile)
+    const uint64_t nt = ceil_div(i.n_subseq, 64);
+    const WsView w = ws_view(workspace, nt);
+    const SyncWs sw = sync_ws(workspace, i.n_subseq);
+    if (i.n_subseq) {
+        st = enqueue_sync(s, sw, w.status, stream);
+        if (st != HD_OK)
+            return st;
+    }
+    return enqueue_chunk_scan(sw.tot, nt, i.n_symbols, w.off, w.partial, w.status, stream);
 }
 
 extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
@@ -895,20 +1243,20 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
         return st;
     if ((s->info.n_symbols && !out) || reinterpret_cast<uintptr_t>(out) % 16 != 0)
         return HD_ERR_ARG;
-    if (m != HD_MODE_GAP)
-        return HD_ERR_UNSUPPORTED;
     const hd_stream_info &i = s->info;
     if (i.n_subseq == 0)
         return HD_OK;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    const WsView w = ws_view(workspace, i.n_chunks);
+    const bool ss = m == HD_MODE_SELF_SYNC;
+    const uint64_t M = ss ? ceil_div(i.n_subseq, 64) : i.n_chunks;
+    const WsView w = ws_view(workspace, M);
     Plan p;
     st = make_plan(s, tune, &p);
     if (st != HD_OK)
         return st;
     GapArgs a;
     a.words = s->words;
-    a.gap = s->gap;
+    a.gap = ss ? sync_ws(workspace, i.n_subseq).gap_s : s->gap;
     a.chunk_off = w.off;
     a.out = out;
     a.status = w.status;
@@ -916,10 +1264,10 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     a.n = i.n_symbols;
     a.B = i.n_bits;
     a.K = i.n_subseq;
-    a.M = i.n_chunks;
+    a.M = M;
     a.n_words = i.n_words;
     a.S = i.subseq_bits;
-    a.C = i.chunk_subseqs;
+    a.C = ss ? 64u : i.chunk_subseqs;
     a.stage = p.stage;
     if (s->table->pair) {
         switch (p.wpg) {
@@ -947,6 +1295,23 @@ extern "C" hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, co
     if (st != HD_OK)
         return st;
     return hd_decode_run(s, out, m, tune, workspace, ws_bytes, hip_stream);
+}
+
+extern "C" hd_status hd_decode_sync_points(const hd_dstream *s, const void *workspace, size_t ws_bytes,
+                                          uint8_t *gap_out, void *hip_stream)
+{
+    hd_status st = check_stream(s, HD_MODE_SELF_SYNC);
+    if (st != HD_OK)
+        return st;
+    if (!workspace || ws_bytes < sync_ws_bytes(s->info.n_subseq) || (s->info.n_subseq && !gap_out))
+        return HD_ERR_ARG;
+    if (s->info.n_subseq == 0)
+        return HD_OK;
+    const SyncWs w = sync_ws(const_cast<void *>(workspace), s->info.n_subseq);
+    return hipMemcpyAsync(gap_out, w.gap_s, s->info.n_subseq, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(hip_stream)) == hipSuccess
+               ? HD_OK
+               : HD_ERR_DEVICE;
 }
 
 extern "C" hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, uint32_t n_streams,

@@ -34,6 +34,7 @@ SIGNATURES = {
     "hd_decode": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp, _sz, _vp]),
     "hd_decode_prepare": (C.c_int, [_vp, C.c_int, _vp, _vp, _sz, _vp]),
     "hd_decode_run": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp, _sz, _vp]),
+    "hd_decode_sync_points": (C.c_int, [_vp, _vp, _sz, _vp, _vp]),
     "hd_decode_batch_workspace_size": (C.c_int, [_vp, _u32, C.c_int, C.POINTER(_sz)]),
     "hd_decode_batch": (C.c_int, [_vp, _u32, _vp, C.c_int, _vp, _vp, _sz, _vp]),
     "hd_decode_status": (C.c_int, [_vp, _vp]),
@@ -269,6 +270,13 @@ def decode_run(ds: DeviceStream, out, workspace, mode: int = MODE_GAP, tune=None
     d = ds.as_c()
     _check(lib().hd_decode_run(C.byref(d), _dev_ptr(out), mode, _tune_ptr(tune), _dev_ptr(workspace),
                                workspace.numel(), _stream_handle(stream)), "hd_decode_run")
+
+
+def decode_sync_points(ds: DeviceStream, workspace, gap_out, stream=None):
+    """Copies the sync points found by a self-sync decode into gap_out (uint8 device tensor)."""
+    d = ds.as_c()
+    _check(lib().hd_decode_sync_points(C.byref(d), _dev_ptr(workspace), workspace.numel(), _dev_ptr(gap_out),
+                                       _stream_handle(stream)), "hd_decode_sync_points")
 
 
 def decode_batch_workspace_size(streams, mode: int = MODE_GAP) -> int:

@@ -1,0 +1,125 @@
+"""GPU parity of the self-synchronizing decode (no gap array, no chunk counts
+read) against the CPU oracle; the sync points found must equal the gap array
+the oracle's encoder emits (the true codeword starts), bit for bit."""
+import numpy as np
+import pytest
+
+import hdsynth
+import oracle
+from hdcase import expected, flush, make_case, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2201_09118_amd import hd  # noqa: F401
+    yield
+
+
+def _check_ss(case, lut_bits=0, tune=None):
+    import torch
+    from paper_2201_09118_amd import hd
+    ds = upload(case, lut_bits, with_gap=False)          # no gap array, no chunk counts on the device
+    n = case.x.size
+    out = torch.full((max(n, 1),), -1, dtype=torch.int16, device="cuda")
+    ws = hd.decode(ds, out, hd.MODE_SELF_SYNC, tune)
+    bits = hd.decode_status_bits(ws)
+    got = out[:n].cpu().numpy().view(np.uint16)
+    want = expected(case)
+    assert bits == 0, f"status bits {bits:#x}"
+    gap = torch.zeros(max(case.enc.gap.size, 1), dtype=torch.uint8, device="cuda")
+    hd.decode_sync_points(ds, ws, gap)
+    found = gap[:case.enc.gap.size].cpu().numpy()
+    sg, _, _ = oracle.selfsync(case.enc.words, case.enc.n_bits, n, case.lengths, case.codes, case.S)
+    assert np.array_equal(found, sg), f"{(found != sg).sum()} sync points differ"
+    assert np.array_equal(found, case.enc.gap)
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError(f"{bad.size} mismatches, first at {bad[:8]}")
+
+
+def test_config1_selfsync():
+    flush("config1 self-sync")
+    _check_ss(make_case(hdsynth.config1_symbols(), 1024, 16, 128, 32))
+
+
+@pytest.mark.parametrize("i", range(16))
+def test_random_streams_selfsync(i):
+    rng = np.random.default_rng(500 + i)
+    S = [32, 64, 128, 256, 512][i % 5]
+    n = [1, 63, 64, 65, 4097, 54321, 200_001, 1000][i % 8]
+    A = int(rng.choice([2, 3, 256, 1024, 4096]))
+    r = float(rng.uniform(0.1, 0.95))
+    x = hdsynth.two_sided_geometric(rng, n, r, A)
+    used = int((np.bincount(x, minlength=A) > 0).sum())
+    L = max(int(np.ceil(np.log2(max(used, 2)))), int(rng.integers(8, 28)))
+    flush(f"self-sync random i={i} S={S} n={n} A={A} L={L}")
+    _check_ss(make_case(x, A, L, S, 32), lut_bits=int(rng.choice([0, 8, 12])))
+
+
+def test_fixed_length_code_never_synchronizes():
+    """3-bit fixed-length code: raw boundaries 128k are off phase for 2 of 3
+    subsequences and never resynchronize; the result must still be exact."""
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 8, 300_000).astype(np.uint16)
+    case = make_case(x, 8, 3, 128, 32)
+    assert set(case.lengths.tolist()) == {3}
+    _check_ss(case)
+
+
+def test_even_length_code_odd_entries():
+    """All codewords 2 bits: paths from odd offsets never meet even ones."""
+    x = np.repeat(np.arange(4, dtype=np.uint16), 20_000)
+    np.random.default_rng(4).shuffle(x)
+    _check_ss(make_case(x, 4, 2, 64, 32))
+
+
+def test_all_one_bit_codes_selfsync():
+    rng = np.random.default_rng(5)
+    x = rng.integers(0, 2, 400_000).astype(np.uint16)
+    _check_ss(make_case(x, 2, 4, 128, 32))
+
+
+def test_long_codes_selfsync():
+    fib = [1, 1]
+    while len(fib) < 30:
+        fib.append(fib[-1] + fib[-2])
+    x = np.repeat(np.arange(30, dtype=np.uint16), fib)
+    np.random.default_rng(6).shuffle(x)
+    case = make_case(x, 30, 27, 256, 32)
+    _check_ss(case, lut_bits=6)
+    _check_ss(case, lut_bits=12)
+
+
+def test_single_symbol_selfsync():
+    _check_ss(make_case(np.full(50_000, 9, np.uint16), 16, 4, 128, 32))
+
+
+def test_selfsync_ignores_gap_and_chunk_counts():
+    """Self-sync reads neither metadata array: garbage there changes nothing."""
+    import torch
+    from paper_2201_09118_amd import hd
+    x = hdsynth.two_sided_geometric(np.random.default_rng(7), 100_000, 0.5, 1024)
+    case = make_case(x, 1024, 20, 128, 32)
+    ds = upload(case)
+    ds.gap.fill_(255)
+    ds.chunk_counts.fill_(7)
+    out = torch.empty(x.size, dtype=torch.int16, device="cuda")
+    ws = hd.decode(ds, out, hd.MODE_SELF_SYNC)
+    assert hd.decode_status(ws) == hd.OK
+    assert np.array_equal(out.cpu().numpy().view(np.uint16), x)
+
+
+@pytest.mark.slow
+def test_config2_full_selfsync():
+    flush("config2 self-sync full")
+    _check_ss(make_case(hdsynth.config2_symbols(), 1024, 24, 128, 32))
+
+
+@pytest.mark.slow
+def test_config3_full_selfsync():
+    flush("config3 self-sync full")
+    _check_ss(make_case(hdsynth.config3_symbols(), 4096, 27, 256, 32))
