@@ -220,25 +220,44 @@ hd_status hd_decode_sync_points(const hd_dstream *s, const void *workspace, size
                                 uint8_t *gap_out, void *hip_stream);
 
 /*
- * Workspace bytes for hd_decode_batch over n_streams streams.
+ * Workspace bytes for hd_decode_batch over n_streams streams (gap mode).
  */
 hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, uint32_t n_streams,
                                          hd_mode m, size_t *bytes);
 
 /*
- * Decodes n_streams independent streams, each with its own table, into
- * outs[i] (device memory, n_symbols of stream i each) in one persistent
- * launch (gap mode) whose workgroups pull (stream, tile) work items from a
- * list ordered by stream; the decode table in LDS is reloaded only when the
- * stream changes.  The paper groups sequences by compression ratio and
- * launches one kernel per group with its own shared-memory size
- * (Sec. IV-C, Algorithm 2); here the grouping is a host-built work list and
- * the per-class parameters come from the autotuner (per_stream may be NULL).
- * m must be HD_MODE_GAP.  Asynchronous; status via hd_decode_status.
+ * Decodes n_streams independent streams, each with its own table, layout and
+ * alphabet, into outs[i] (device memory, n_symbols of stream i, 16-byte
+ * aligned) with one segmented chunk-offset scan and one persistent decode
+ * launch.  The paper groups sequences by compression ratio and launches one
+ * kernel per group, each with its own shared-memory size (Sec. IV-C, Alg. 2);
+ * here workgroups pull (stream, group of tiles) items from one counter and
+ * reload the LDS decode table only when the stream changes.  per_stream, when
+ * not NULL, holds n_streams tunes: stage_symbols per stream (the launch
+ * reserves the largest) and waves_per_group of per_stream[0] for the launch.
+ * m must be HD_MODE_GAP (HD_ERR_UNSUPPORTED otherwise).  Per-call
+ * descriptors are uploaded through library-owned pinned staging, without a
+ * host wait.  Asynchronous on hip_stream; the status word (hd_decode_status)
+ * covers every stream of the batch.
  */
 hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_streams, uint16_t *const *outs,
-                          hd_mode m, const hd_tune *tune, void *workspace, size_t ws_bytes,
+                          hd_mode m, const hd_tune *per_stream, void *workspace, size_t ws_bytes,
                           void *hip_stream);
+
+/*
+ * Decode-parameter autotuning on a sample stream.  The paper tunes the
+ * shared-memory buffer per call from each sequence's compression ratio
+ * (Sec. IV-C, Alg. 2, Table I) and compares against a brute-force sweep;
+ * here the sweep itself is the tuner, run once per stream class and cached
+ * by the caller: hd_decode_run is timed with HIP events (median of three
+ * after a warm-up) for waves_per_group in {4, 8, 16} times staging sizes of
+ * 0.5x .. 2x the expected tile output, and the fastest tune goes to *best
+ * (its time to *best_ms when not NULL).  out and workspace are as for
+ * hd_decode on this sample (their contents are overwritten).  Synchronous:
+ * waits for hip_stream.
+ */
+hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *out, void *workspace,
+                      size_t ws_bytes, void *hip_stream, hd_tune *best, float *best_ms);
 
 /*
  * Waits for hip_stream, then reads the status word the last decode on this
@@ -258,6 +277,40 @@ hd_status hd_decode_status(const void *workspace, void *hip_stream);
  * self-synchronization point.  Waits for hip_stream first.
  */
 uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream);
+
+/* ------------------------------------------------------------- serving -- */
+
+/*
+ * A decode server with continuous batching (no counterpart in the paper,
+ * which measures single calls).  It owns one device arena of hbm_budget
+ * bytes; every admitted request's output (n_symbols uint16) and every
+ * batch's workspace come from it, so the in-flight device footprint never
+ * exceeds the budget.  A scheduler thread admits queued requests in arrival
+ * order while they fit, launches each admitted group as one hd_decode_batch
+ * on one of n_hip_streams streams (default priority), and retires batches by
+ * event.  Requests arriving while batches run are admitted as memory and
+ * stream slots free up; their work overlaps on the device.  Request streams
+ * (device buffers and tables) must stay alive until the request completes.
+ */
+typedef struct hd_server hd_server;
+
+hd_status hd_server_create(size_t hbm_budget, uint32_t n_hip_streams, uint32_t max_batch,
+                           hd_server **out);
+/* Waits for running batches, drops requests never admitted, frees the arena. */
+void hd_server_destroy(hd_server *s);
+/* Queues a gap-mode decode of *stream; HD_ERR_NOMEM when its output plus
+ * workspace exceed the whole budget (it could never be admitted). */
+hd_status hd_server_submit(hd_server *s, const hd_dstream *stream, uint64_t *request_id);
+/* Non-blocking: up to cap ids of requests completed since the last poll. */
+hd_status hd_server_poll(hd_server *s, uint64_t *done_ids, uint32_t cap, uint32_t *n_done);
+/* A completed request: device output (valid until release), its batch's
+ * decode status, and submit/completion times in seconds (steady clock). */
+hd_status hd_server_result(hd_server *s, uint64_t id, const uint16_t **out, hd_status *status,
+                           double *t_submit, double *t_done);
+/* Returns a completed request's output memory to the arena. */
+hd_status hd_server_release(hd_server *s, uint64_t id);
+hd_status hd_server_stats(hd_server *s, uint64_t *n_batches, uint64_t *n_done, uint64_t *queued,
+                          uint64_t *arena_used, uint64_t *arena_peak);
 
 /* Static description of a status code. */
 const char *hd_status_str(hd_status s);

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhd.so")
-SOURCES = ["hd_host.cpp", "hd_device.hip"]
+SOURCES = ["hd_host.cpp", "hd_device.hip", "hd_serve.cpp"]
 ARCH = os.environ.get("HD_OFFLOAD_ARCH", "gfx950")
 
 
@@ -29,6 +29,8 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(tmpdir, src + ".o")
         cmd = [hipcc()] + common + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if src == "hd_serve.cpp":
+            cmd += ["-pthread"]
         if src.endswith(".hip"):
             cmd += ["-x", "hip", f"--offload-arch={ARCH}",
                     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -38,7 +40,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + f".tmp{os.getpid()}"
-    link = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    link = [hipcc(), "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)

@@ -492,64 +492,49 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_finish(const uint32_t *__
 
 constexpr uint32_t kMaxUnitsPerLane = 16;   // subsequences of at most 512 bits
 
-struct GapArgs {
+// One stream as the decode kernels see it.
+struct StreamDev {
     const uint32_t *words;
     const uint8_t *gap;
-    const uint64_t *chunk_off;   // [M + 1]
+    const uint64_t *chunk_off;   // [M + 1] output index of each chunk
     uint16_t *out;
-    uint32_t *status;
-    TableView tab;
     uint64_t n, B, K, M, n_words;
     uint32_t S, C, stage;        // stage: staging symbols per wave (multiple of 64)
 };
 
+struct GapArgs {
+    StreamDev sd;
+    uint32_t *status;
+    TableView tab;
+};
+
 // LDS of one wave's private area: the transposed unit copy TT (S/32 + 2
-// words per lane, 64 lanes) and the staging tile.
+// words per lane, 64 lanes), the staging tile, and 64 dummy uint16 slots
+// that absorb untaken second-symbol stores.
 __host__ __device__ __forceinline__ uint32_t wave_units_bytes(uint32_t S)
 {
     return ((S >> 5) + 2) * 64 * 4;
 }
 
-// ... plus 64 dummy uint16 slots that absorb untaken second-symbol stores.
 __host__ __device__ __forceinline__ uint32_t wave_area_bytes(uint32_t S, uint32_t stage)
 {
     return wave_units_bytes(S) + 2 * stage + 128;
 }
 
-template <int WPG, bool PAIR>
-__global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
-{
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const TableView &g = a.tab;
-    const SmemTable st = carve_table(smem, g.k1);
-    load_table(st, g);
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const uint32_t S = a.S;
-    const uint32_t wps = S >> 5;
-    unsigned char *area = smem + table_lds_bytes(g.k1) + wv * wave_area_bytes(S, a.stage);
-    uint32_t *TTl = reinterpret_cast<uint32_t *>(area) + lane;
-    uint16_t *stage = reinterpret_cast<uint16_t *>(area + wave_units_bytes(S));
-    uint16_t *dummy = stage + a.stage + lane;
-    const uint32_t sh = 32 - g.k1;
-    const uint32_t PB = a.stage - 8;
-
-    uint32_t err = 0;
-    const uint64_t ntiles = (a.K + 63) >> 6;
-    const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * WPG;
-
-    // Tile inputs travel through registers one tile ahead: while tile t is
-    // decoded, the units, gap bytes and chunk offsets of the wavefront's next
-    // tile are already in flight.
+// A lane's inputs for one tile: its subsequence's units and the next unit,
+// its gap byte and its successor's, and the output offsets bounding its
+// chunk.  Loaded into registers (one tile ahead in the single-stream kernel).
+struct TileIn {
     uint32_t pw[kMaxUnitsPerLane];
-    uint32_t pwn = 0, pgk = 0, pgn = 0;
-    uint64_t pco_lo = 0, pco_hi = 0;
-    auto prefetch = [&](uint64_t tt) {
-        const uint64_t k = (tt << 6) + lane;
-        if (tt < ntiles && k < a.K) {
-            const uint32_t *src = a.words + k * wps;
+    uint32_t pwn = 0, gk = 0, gn = 0;
+    uint64_t c_lo = 0, c_hi = 0;
+
+    __device__ __forceinline__ void load(const StreamDev &sd, uint64_t t, uint64_t ntiles, int lane)
+    {
+        const uint32_t wps = sd.S >> 5;
+        const uint64_t k = (t << 6) + lane;
+        if (t < ntiles && k < sd.K) {
+            const uint32_t *src = sd.words + k * wps;
             if ((wps & 3) == 0) {
 #pragma unroll
                 for (uint32_t i = 0; i < kMaxUnitsPerLane / 4; ++i)
@@ -566,20 +551,16 @@ __global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
                     if (i < wps)
                         pw[i] = src[i];
             }
-            pwn = src[wps];                          // (k+1)*S/32 < n_words for k < K
-            pgk = a.gap[k];
-            pgn = k + 1 < a.K ? a.gap[k + 1] : 0u;
-            pco_lo = a.chunk_off[k / a.C];            // bounds of this lane's chunk
-            pco_hi = a.chunk_off[k / a.C + 1];        // (k / C + 1 <= M for k < K)
+            pwn = src[wps];                           // (k+1)*S/32 < n_words for k < K
+            gk = sd.gap[k];
+            gn = k + 1 < sd.K ? sd.gap[k + 1] : 0u;
+            c_lo = sd.chunk_off[k / sd.C];             // bounds of this lane's chunk
+            c_hi = sd.chunk_off[k / sd.C + 1];         // (k / C + 1 <= M for k < K)
         }
-    };
-    uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv;
-    prefetch(t);
-    for (; t < ntiles; t += tstride) {
-        const uint64_t k0 = t << 6;
-        const uint64_t k = k0 + lane;
-        const bool act = k < a.K;
-        // 1. the prefetched units go to this lane's column of TT
+    }
+
+    __device__ __forceinline__ void store_units(uint32_t *TTl, uint32_t wps, bool act) const
+    {
         if (act) {
 #pragma unroll
             for (uint32_t i = 0; i < kMaxUnitsPerLane; ++i)
@@ -587,114 +568,161 @@ __global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
                     TTl[(i + 1) * 64] = pw[i];
             TTl[(wps + 1) * 64] = pwn;
         }
-        const uint32_t gk = act ? pgk : 0u;
-        const uint32_t gn = pgn;
-        const uint64_t c_lo = pco_lo, c_hi = pco_hi;
-        prefetch(t + tstride);
+    }
+};
+
+// Steps 2-4 for one wavefront tile whose units are already in TT.
+template <bool PAIR>
+__device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int lane, uint32_t gk_in,
+                                            uint32_t gn, uint64_t c_lo, uint64_t c_hi, const uint32_t *TTl,
+                                            uint16_t *stage, uint16_t *dummy, const SmemTable &st,
+                                            const TableView &g, uint32_t sh, uint32_t &err)
+{
+    const uint32_t S = sd.S;
+    const uint32_t PB = sd.stage - 8;
+    const uint64_t k0 = t << 6;
+    const uint64_t k = k0 + lane;
+    const bool act = k < sd.K;
+    const uint32_t gk = act ? gk_in : 0u;
+
+    // 2. count pass (positions relative to the lane's subsequence start)
+    uint32_t re = 0;
+    if (act) {
+        const uint64_t e = (k + 1) * S < sd.B ? (k + 1) * S : sd.B;
+        re = static_cast<uint32_t>(e - k * S);
+    }
+    uint32_t rs = gk;
+    if (gk >= 32) {
+        err |= kErrGapRange;
+        rs = re;
+    }
+    if (rs > re)
+        rs = re;
+    const uint32_t qe = re + 31;
+    uint32_t cnt = 0;
+    uint32_t q = rs + 31;
+    {
+        // both codewords of a pair are taken; a second codeword that starts
+        // at or past the end is given back after the loop
+        uint32_t qm = q, l2 = 0;
+        while (q < qe) {
+            uint32_t s1, s2, l1;
+            lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
+            qm = q + l1;
+            q = qm + l2;
+            cnt += 1 + (l2 != 0);
+        }
+        if (PAIR && l2 != 0 && qm >= qe) {
+            --cnt;
+            q = qm;
+        }
+    }
+    // the walk must stop exactly on the next subsequence's start
+    if (act) {
+        const uint32_t expect = (k + 1 < sd.K) ? S + gn : re;
+        if (q - 31 != expect)
+            err |= kErrLaneEnd;
+    }
+
+    // 3. output indices: wavefront scan inside the tile; the tile starts at
+    //    the output offset of its first chunk (lane 0's chunk)
+    const uint32_t incl = wave_incl_scan(cnt, lane);
+    const uint32_t excl = incl - cnt;
+    const uint32_t total = __shfl(incl, 63, 64);
+    const uint64_t gbase = __shfl(c_lo, 0, 64);
+    {
+        const uint32_t cl = lane % sd.C;
+        const uint32_t excl_first = __shfl(excl, lane - cl, 64);
+        if (act && (cl == sd.C - 1 || k == sd.K - 1)) {
+            if (gbase + excl_first != c_lo || gbase + incl != c_hi)
+                err |= kErrChunkSum;
+        }
+    }
+
+    // 4. decode into LDS staging, flush with 16-byte stores
+    const uint32_t a0 = static_cast<uint32_t>(gbase & 7);
+    q = rs + 31;
+    uint32_t j = 0;
+    for (uint32_t pb = 0; pb < total; pb += PB) {
+        const uint32_t lim_rel = pb + PB;
+        const uint32_t jmax = lim_rel > excl ? min(cnt, lim_rel - excl) : 0u;
+        // dst index of symbol j: a0 + excl + j - pb (>= a0 whenever j < jmax)
+        uint16_t *dst = stage + (static_cast<int32_t>(a0 + excl) - static_cast<int32_t>(pb));
+        while (j < jmax) {
+            uint32_t s1, s2, l1, l2;
+            lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
+            dst[j] = static_cast<uint16_t>(s1);
+            ++j;
+            if (PAIR) {
+                // second codeword: stored when it is this lane's and in this
+                // pass, else written to the lane's dummy slot
+                const bool two = l2 != 0 && j < jmax;
+                *(two ? dst + j : dummy) = static_cast<uint16_t>(s2);
+                j += two;
+                l1 += two ? l2 : 0u;
+            }
+            q += l1;
+        }
         wave_lds_sync();
-
-        // 2. count pass (positions relative to the lane's subsequence start)
-        uint32_t re = 0;
-        if (act) {
-            const uint64_t e = (k + 1) * S < a.B ? (k + 1) * S : a.B;
-            re = static_cast<uint32_t>(e - k * S);
+        uint64_t g0 = gbase + pb;
+        uint64_t g1 = gbase + min(lim_rel, total);
+        if (g1 > sd.n) {
+            err |= kErrOutRange;
+            g1 = sd.n;
         }
-        uint32_t rs = gk;
-        if (gk >= 32) {
-            err |= kErrGapRange;
-            rs = re;
-        }
-        if (rs > re)
-            rs = re;
-        const uint32_t qe = re + 31;
-        uint32_t cnt = 0;
-        uint32_t q = rs + 31;
-        {
-            // both codewords of a pair are taken; a second codeword that
-            // starts at or past the end is given back after the loop
-            uint32_t qm = q, l2 = 0;
-            while (q < qe) {
-                uint32_t s1, s2, l1;
-                lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
-                qm = q + l1;
-                q = qm + l2;
-                cnt += 1 + (l2 != 0);
-            }
-            if (PAIR && l2 != 0 && qm >= qe) {
-                --cnt;
-                q = qm;
-            }
-        }
-        // the walk must stop exactly on the next subsequence's start
-        if (act) {
-            const uint32_t expect = (k + 1 < a.K) ? S + gn : re;
-            if (q - 31 != expect)
-                err |= kErrLaneEnd;
-        }
-
-        // 3. output indices: wavefront scan inside the tile; the tile starts
-        //    at the output offset of its first chunk (lane 0's chunk)
-        const uint32_t incl = wave_incl_scan(cnt, lane);
-        const uint32_t excl = incl - cnt;
-        const uint32_t total = __shfl(incl, 63, 64);
-        const uint64_t gbase = __shfl(c_lo, 0, 64);
-        {
-            const uint32_t cl = lane % a.C;
-            const uint32_t excl_first = __shfl(excl, lane - cl, 64);
-            if (act && (cl == a.C - 1 || k == a.K - 1)) {
-                if (gbase + excl_first != c_lo || gbase + incl != c_hi)
-                    err |= kErrChunkSum;
-            }
-        }
-
-        // 4. decode into LDS staging, flush with 16-byte stores
-        const uint32_t a0 = static_cast<uint32_t>(gbase & 7);
-        q = rs + 31;
-        uint32_t j = 0;
-        for (uint32_t pb = 0; pb < total; pb += PB) {
-            const uint32_t lim_rel = pb + PB;
-            const uint32_t jmax = lim_rel > excl ? min(cnt, lim_rel - excl) : 0u;
-            // dst index of symbol j: a0 + excl + j - pb (>= a0 whenever j < jmax)
-            uint16_t *dst = stage + (static_cast<int32_t>(a0 + excl) - static_cast<int32_t>(pb));
-            while (j < jmax) {
-                uint32_t s1, s2, l1, l2;
-                lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
-                dst[j] = static_cast<uint16_t>(s1);
-                ++j;
-                if (PAIR) {
-                    // second codeword: stored when it is this lane's and in
-                    // this pass, else written to the lane's dummy slot
-                    const bool two = l2 != 0 && j < jmax;
-                    *(two ? dst + j : dummy) = static_cast<uint16_t>(s2);
-                    j += two;
-                    l1 += two ? l2 : 0u;
-                }
-                q += l1;
-            }
-            wave_lds_sync();
-            uint64_t g0 = gbase + pb;
-            uint64_t g1 = gbase + min(lim_rel, total);
-            if (g1 > a.n) {
-                err |= kErrOutRange;
-                g1 = a.n;
-            }
-            if (g0 < g1) {
-                const uint64_t gb0 = g0 & ~uint64_t(7);
-                const uint32_t ngroups = static_cast<uint32_t>((g1 - gb0 + 7) >> 3);
-                for (uint32_t gi = lane; gi < ngroups; gi += 64) {
-                    const uint64_t gs = gb0 + 8ull * gi;
-                    if (gs >= g0 && gs + 8 <= g1) {
-                        *reinterpret_cast<uint4 *>(a.out + gs) =
-                            *reinterpret_cast<const uint4 *>(stage + 8 * gi);
-                    } else {
-                        for (uint32_t e = 0; e < 8; ++e)
-                            if (gs + e >= g0 && gs + e < g1)
-                                a.out[gs + e] = stage[8 * gi + e];
-                    }
+        if (g0 < g1) {
+            const uint64_t gb0 = g0 & ~uint64_t(7);
+            const uint32_t ngroups = static_cast<uint32_t>((g1 - gb0 + 7) >> 3);
+            for (uint32_t gi = lane; gi < ngroups; gi += 64) {
+                const uint64_t gs = gb0 + 8ull * gi;
+                if (gs >= g0 && gs + 8 <= g1) {
+                    *reinterpret_cast<uint4 *>(sd.out + gs) = *reinterpret_cast<const uint4 *>(stage + 8 * gi);
+                } else {
+                    for (uint32_t e = 0; e < 8; ++e)
+                        if (gs + e >= g0 && gs + e < g1)
+                            sd.out[gs + e] = stage[8 * gi + e];
                 }
             }
-            wave_lds_sync();
         }
+        wave_lds_sync();
+    }
+}
+
+template <int WPG, bool PAIR>
+__global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const TableView &g = a.tab;
+    const SmemTable st = carve_table(smem, g.k1);
+    load_table(st, g);
+    __syncthreads();
+
+    const StreamDev &sd = a.sd;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const uint32_t wps = sd.S >> 5;
+    unsigned char *area = smem + table_lds_bytes(g.k1) + wv * wave_area_bytes(sd.S, sd.stage);
+    uint32_t *TTl = reinterpret_cast<uint32_t *>(area) + lane;
+    uint16_t *stage = reinterpret_cast<uint16_t *>(area + wave_units_bytes(sd.S));
+    uint16_t *dummy = stage + sd.stage + lane;
+    const uint32_t sh = 32 - g.k1;
+
+    uint32_t err = 0;
+    const uint64_t ntiles = (sd.K + 63) >> 6;
+    const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * WPG;
+    // Tile inputs travel through registers one tile ahead: while tile t is
+    // decoded, the inputs of the wavefront's next tile are in flight.
+    TileIn in;
+    uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv;
+    in.load(sd, t, ntiles, lane);
+    for (; t < ntiles; t += tstride) {
+        const bool act = (t << 6) + lane < sd.K;
+        in.store_units(TTl, wps, act);
+        const uint32_t gk = in.gk, gn = in.gn;
+        const uint64_t c_lo = in.c_lo, c_hi = in.c_hi;
+        in.load(sd, t + tstride, ntiles, lane);
+        wave_lds_sync();
+        decode_tile<PAIR>(sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, g, sh, err);
     }
     if (err)
         atomicOr(a.status, err);
@@ -963,6 +991,173 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
     }
 }
 
+// ------------------------------------------------------------------------
+// Batched persistent decode: many streams, one launch
+// ------------------------------------------------------------------------
+//
+// The paper groups sequences by compression ratio and launches one decode
+// kernel per group, each with its own shared-memory size, on separate
+// streams (Sec. IV-C, Alg. 2).  Here one persistent launch covers every
+// stream of a batch: a work item is a group of WPG consecutive wavefront
+// tiles of one stream (items never straddle streams), items are numbered
+// stream by stream, and each workgroup pulls items from an atomic counter,
+// reloading the decode table into LDS only when its next item belongs to
+// another stream.  Per-stream chunk offsets come from one segmented scan.
+
+struct BatchStreamDev {
+    StreamDev sd;
+    TableView tab;
+    uint64_t item0;       // first work item of this stream
+    uint64_t ntiles;
+    uint32_t pair;
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    const BatchStreamDev *streams;
+    uint32_t n_streams;
+    uint64_t n_items;
+    unsigned long long *counter;
+    uint32_t *status;
+    uint32_t S_alloc, stage_alloc, k1_alloc;
+};
+
+template <int WPG>
+__global__ __launch_bounds__(WPG * 64) void k_decode_batch(BatchArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ unsigned long long s_item;
+    __shared__ uint32_t s_stream;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    unsigned char *area = smem + table_lds_bytes(a.k1_alloc) + wv * wave_area_bytes(a.S_alloc, a.stage_alloc);
+    uint32_t *TTl = reinterpret_cast<uint32_t *>(area) + lane;
+    uint16_t *stage = reinterpret_cast<uint16_t *>(area + wave_units_bytes(a.S_alloc));
+    uint16_t *dummy = stage + a.stage_alloc + lane;
+    uint32_t err = 0;
+    uint32_t cur = 0xffffffffu;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const unsigned long long item = atomicAdd(a.counter, 1ull);
+            uint32_t lo = 0, hi = a.n_streams;          // last stream with item0 <= item
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (a.streams[mid].item0 <= item)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            s_item = item;
+            s_stream = lo;
+        }
+        __syncthreads();
+        const unsigned long long item = s_item;
+        const uint32_t si = s_stream;
+        if (item >= a.n_items)
+            break;
+        const BatchStreamDev &bs = a.streams[si];
+        const SmemTable st = carve_table(smem, bs.tab.k1);
+        if (si != cur) {
+            load_table(st, bs.tab);
+            cur = si;
+        }
+        __syncthreads();
+        const uint64_t t = (item - bs.item0) * WPG + wv;
+        if (t < bs.ntiles) {
+            const bool act = (t << 6) + lane < bs.sd.K;
+            TileIn in;
+            in.load(bs.sd, t, bs.ntiles, lane);
+            in.store_units(TTl, bs.sd.S >> 5, act);
+            wave_lds_sync();
+            const uint32_t sh = 32 - bs.tab.k1;
+            if (bs.pair)
+                decode_tile<true>(bs.sd, t, lane, in.gk, in.gn, in.c_lo, in.c_hi, TTl, stage, dummy, st,
+                                  bs.tab, sh, err);
+            else
+                decode_tile<false>(bs.sd, t, lane, in.gk, in.gn, in.c_lo, in.c_hi, TTl, stage, dummy, st,
+                                   bs.tab, sh, err);
+        }
+        __syncthreads();        // the table may change with the next item
+    }
+    if (err)
+        atomicOr(a.status, err);
+}
+
+// Segmented scan of every stream's chunk counts.
+struct BatchScanStream {
+    const uint32_t *cc;
+    uint64_t *off;            // [M + 1]
+    uint64_t M, n;
+    uint32_t blk0, nblk;      // the stream's blocks in the global block list
+};
+
+struct BatchScanBlock {
+    uint32_t stream, blk;
+};
+
+__global__ __launch_bounds__(kScanThreads) void k_bscan_reduce(const BatchScanStream *ss, const BatchScanBlock *bl,
+                                                               uint64_t *partial, uint32_t *status,
+                                                               unsigned long long *counter)
+{
+    __shared__ uint64_t sh[kScanThreads / 64];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *status = 0;
+        *counter = 0;
+    }
+    const BatchScanBlock b = bl[blockIdx.x];
+    const BatchScanStream st = ss[b.stream];
+    const uint64_t b0 = static_cast<uint64_t>(b.blk) * kScanBlock;
+    uint64_t s = 0;
+    for (int i = 0; i < kScanPerThread; ++i) {
+        const uint64_t c = b0 + static_cast<uint64_t>(i) * kScanThreads + threadIdx.x;
+        if (c < st.M)
+            s += st.cc[c];
+    }
+    s = block_sum_u64(s, sh);
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_bscan_finish(const BatchScanStream *ss, const BatchScanBlock *bl,
+                                                               const uint64_t *partial, uint32_t *status)
+{
+    __shared__ uint64_t sh[kScanThreads / 64];
+    __shared__ uint64_t tsum[kScanThreads];
+    const BatchScanBlock b = bl[blockIdx.x];
+    const BatchScanStream st = ss[b.stream];
+    uint64_t pre = 0;
+    for (uint32_t i = threadIdx.x; i < b.blk; i += blockDim.x)
+        pre += partial[st.blk0 + i];
+    pre = block_sum_u64(pre, sh);
+    const uint64_t my0 = static_cast<uint64_t>(b.blk) * kScanBlock + static_cast<uint64_t>(threadIdx.x) * kScanPerThread;
+    uint32_t v[kScanPerThread];
+    uint64_t s = 0;
+    for (int i = 0; i < kScanPerThread; ++i) {
+        v[i] = (my0 + i < st.M) ? st.cc[my0 + i] : 0u;
+        s += v[i];
+    }
+    tsum[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        const uint64_t o = threadIdx.x >= (unsigned)d ? tsum[threadIdx.x - d] : 0;
+        __syncthreads();
+        tsum[threadIdx.x] += o;
+        __syncthreads();
+    }
+    uint64_t run = pre + tsum[threadIdx.x] - s;
+    for (int i = 0; i < kScanPerThread; ++i) {
+        if (my0 + i < st.M)
+            st.off[my0 + i] = run;
+        run += v[i];
+    }
+    if (b.blk == st.nblk - 1 && threadIdx.x == kScanThreads - 1) {
+        const uint64_t total = pre + tsum[kScanThreads - 1];
+        st.off[st.M] = total;
+        if (total != st.n)
+            atomicOr(status, kErrTotal);
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------
@@ -1013,21 +1208,23 @@ hd_status check_stream(const hd_dstream *s, hd_mode m)
     return HD_OK;
 }
 
+// Default staging: a wavefront tile of 64 subsequences decodes about
+// 64 * S / (mean code length) symbols; a quarter of headroom keeps nearly
+// every tile to one staging pass.
+uint32_t auto_stage_for(const hd_stream_info &si)
+{
+    const double per_tile = si.n_bits ? 64.0 * si.subseq_bits * double(si.n_symbols) / double(si.n_bits) : 1024.0;
+    uint32_t st = static_cast<uint32_t>(per_tile * 1.25) + 64;
+    return std::min<uint32_t>(8192, std::max<uint32_t>(512, (st + 255) / 256 * 256));
+}
+
 hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
 {
     const DeviceInfo *dev = device_info();
     if (!dev)
         return HD_ERR_DEVICE;
-    // Default staging: a wavefront tile of 64 subsequences decodes about
-    // 64 * S / (mean code length) symbols; a quarter of headroom keeps nearly
-    // every tile to one staging pass.
-    const hd_stream_info &si = s->info;
-    const double per_tile = si.n_bits ? 64.0 * si.subseq_bits * double(si.n_symbols) / double(si.n_bits)
-                                      : 1024.0;
-    uint32_t auto_stage = static_cast<uint32_t>(per_tile * 1.25) + 64;
-    auto_stage = std::min<uint32_t>(8192, std::max<uint32_t>(512, (auto_stage + 255) / 256 * 256));
     p->wpg = tune && tune->waves_per_group ? tune->waves_per_group : 4;
-    p->stage = tune && tune->stage_symbols ? tune->stage_symbols : auto_stage;
+    p->stage = tune && tune->stage_symbols ? tune->stage_symbols : auto_stage_for(s->info);
     if (p->wpg != 4 && p->wpg != 8 && p->wpg != 16)
         return HD_ERR_ARG;
     if (p->stage < 256 || p->stage > 16384 || p->stage % 64)
@@ -1255,20 +1452,20 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     if (st != HD_OK)
         return st;
     GapArgs a;
-    a.words = s->words;
-    a.gap = ss ? sync_ws(workspace, i.n_subseq).gap_s : s->gap;
-    a.chunk_off = w.off;
-    a.out = out;
+    a.sd.words = s->words;
+    a.sd.gap = ss ? sync_ws(workspace, i.n_subseq).gap_s : s->gap;
+    a.sd.chunk_off = w.off;
+    a.sd.out = out;
+    a.sd.n = i.n_symbols;
+    a.sd.B = i.n_bits;
+    a.sd.K = i.n_subseq;
+    a.sd.M = M;
+    a.sd.n_words = i.n_words;
+    a.sd.S = i.subseq_bits;
+    a.sd.C = ss ? 64u : i.chunk_subseqs;
+    a.sd.stage = p.stage;
     a.status = w.status;
     a.tab = view_of(s->table);
-    a.n = i.n_symbols;
-    a.B = i.n_bits;
-    a.K = i.n_subseq;
-    a.M = M;
-    a.n_words = i.n_words;
-    a.S = i.subseq_bits;
-    a.C = ss ? 64u : i.chunk_subseqs;
-    a.stage = p.stage;
     if (s->table->pair) {
         switch (p.wpg) {
         case 4: return launch_gap<4, true>(a, p, stream);
@@ -1314,20 +1511,307 @@ extern "C" hd_status hd_decode_sync_points(const hd_dstream *s, const void *work
                : HD_ERR_DEVICE;
 }
 
+namespace {
+
+// Workspace layout of a batch: header (status, item counter), stream
+// descriptors, scan descriptors, scan block list, scan partials, then every
+// stream's chunk offsets.
+struct BatchLayout {
+    size_t desc, sdesc, blocks, partial, offs, total;
+    std::vector<size_t> off_at;   // byte offset of each stream's chunk offsets
+    uint32_t nblk_total;
+};
+
+hd_status batch_layout(const hd_dstream *streams, uint32_t n, BatchLayout *L)
+{
+    size_t p = kWsHeader;
+    L->desc = p;
+    p += align_up(sizeof(BatchStreamDev) * n, 256);
+    L->sdesc = p;
+    p += align_up(sizeof(BatchScanStream) * n, 256);
+    uint64_t nb = 0;
+    for (uint32_t i = 0; i < n; ++i)
+        nb += std::max<uint64_t>(1, ceil_div(streams[i].info.n_chunks, kScanBlock));
+    if (nb > 0x7fffffffu)
+        return HD_ERR_UNSUPPORTED;
+    L->nblk_total = static_cast<uint32_t>(nb);
+    L->blocks = p;
+    p += align_up(sizeof(BatchScanBlock) * nb, 256);
+    L->partial = p;
+    p += align_up(8 * nb, 256);
+    L->offs = p;
+    L->off_at.resize(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        L->off_at[i] = p;
+        p += align_up(8 * (streams[i].info.n_chunks + 1), 256);
+    }
+    L->total = p;
+    return HD_OK;
+}
+
+// Pinned host staging for per-call descriptors.  A buffer is reused only
+// after the event recorded behind its last upload has completed, so uploads
+// never wait for the host and never race with earlier calls.
+struct StagingBuf {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+};
+
+std::mutex g_stage_mu;
+std::vector<StagingBuf *> g_stage;
+
+StagingBuf *staging_acquire(size_t bytes)
+{
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    for (StagingBuf *b : g_stage) {
+        if (b->busy && hipEventQuery(b->done) == hipSuccess)
+            b->busy = false;
+        if (!b->busy && b->cap >= bytes) {
+            b->busy = true;
+            return b;
+        }
+    }
+    StagingBuf *b = new StagingBuf();
+    if (hipHostMalloc(&b->host, bytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return nullptr;
+    }
+    b->cap = bytes;
+    b->busy = true;
+    g_stage.push_back(b);
+    return b;
+}
+
+template <int WPG>
+hd_status launch_batch(const BatchArgs &a, uint32_t lds, hipStream_t stream)
+{
+    static bool attr_set = false;
+    const DeviceInfo *dev = device_info();
+    if (!attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_batch<WPG>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(dev->lds_per_block) - 64) != hipSuccess)
+            return HD_ERR_DEVICE;
+        attr_set = true;
+    }
+    uint32_t fit = static_cast<uint32_t>(dev->lds_per_cu / (lds + 64));
+    fit = std::max<uint32_t>(1, std::min<uint32_t>(fit, 32 / WPG));
+    const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(a.n_items, uint64_t(dev->cus) * fit)));
+    hipLaunchKernelGGL(k_decode_batch<WPG>, dim3(grid), dim3(WPG * 64), lds, stream, a);
+    return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
+}
+
+}  // namespace
+
 extern "C" hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, uint32_t n_streams,
                                                     hd_mode m, size_t *bytes)
 {
-    (void)streams; (void)n_streams; (void)m; (void)bytes;
-    return HD_ERR_UNSUPPORTED;
+    if (!bytes || (n_streams && !streams))
+        return HD_ERR_ARG;
+    if (m != HD_MODE_GAP)
+        return HD_ERR_UNSUPPORTED;
+    for (uint32_t i = 0; i < n_streams; ++i) {
+        hd_status st = check_stream(&streams[i], m);
+        if (st != HD_OK)
+            return st;
+    }
+    BatchLayout L;
+    hd_status st = batch_layout(streams, n_streams, &L);
+    if (st != HD_OK)
+        return st;
+    *bytes = L.total;
+    return HD_OK;
 }
 
 extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_streams,
-                                     uint16_t *const *outs, hd_mode m, const hd_tune *tune,
+                                     uint16_t *const *outs, hd_mode m, const hd_tune *per_stream,
                                      void *workspace, size_t ws_bytes, void *hip_stream)
 {
-    (void)streams; (void)n_streams; (void)outs; (void)m; (void)tune; (void)workspace;
-    (void)ws_bytes; (void)hip_stream;
-    return HD_ERR_UNSUPPORTED;
+    if (n_streams == 0)
+        return HD_OK;
+    if (!streams || !outs || !workspace || reinterpret_cast<uintptr_t>(workspace) % 256)
+        return HD_ERR_ARG;
+    size_t need = 0;
+    hd_status st = hd_decode_batch_workspace_size(streams, n_streams, m, &need);
+    if (st != HD_OK)
+        return st;
+    if (ws_bytes < need)
+        return HD_ERR_ARG;
+    const DeviceInfo *dev = device_info();
+    if (!dev)
+        return HD_ERR_DEVICE;
+    BatchLayout L;
+    st = batch_layout(streams, n_streams, &L);
+    if (st != HD_OK)
+        return st;
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+
+    const uint32_t wpg = per_stream && per_stream[0].waves_per_group ? per_stream[0].waves_per_group : 4;
+    if (wpg != 4 && wpg != 8 && wpg != 16)
+        return HD_ERR_ARG;
+    uint32_t S_alloc = 32, stage_alloc = 256, k1_alloc = 1;
+    std::vector<BatchStreamDev> d(n_streams);
+    std::vector<BatchScanStream> ss(n_streams);
+    std::vector<BatchScanBlock> bl;
+    bl.reserve(L.nblk_total);
+    uint64_t items = 0;
+    for (uint32_t i = 0; i < n_streams; ++i) {
+        const hd_dstream &s = streams[i];
+        const hd_stream_info &si = s.info;
+        if ((si.n_symbols && !outs[i]) || reinterpret_cast<uintptr_t>(outs[i]) % 16 ||
+            reinterpret_cast<uintptr_t>(s.words) % 16)
+            return HD_ERR_ARG;
+        if (64 % si.chunk_subseqs)
+            return HD_ERR_UNSUPPORTED;
+        uint32_t stage = per_stream && per_stream[i].stage_symbols ? per_stream[i].stage_symbols : auto_stage_for(si);
+        if (stage < 256 || stage > 16384 || stage % 64)
+            return HD_ERR_ARG;
+        BatchStreamDev &b = d[i];
+        b.sd.words = s.words;
+        b.sd.gap = s.gap;
+        b.sd.chunk_off = reinterpret_cast<const uint64_t *>(ws + L.off_at[i]);
+        b.sd.out = outs[i];
+        b.sd.n = si.n_symbols;
+        b.sd.B = si.n_bits;
+        b.sd.K = si.n_subseq;
+        b.sd.M = si.n_chunks;
+        b.sd.n_words = si.n_words;
+        b.sd.S = si.subseq_bits;
+        b.sd.C = si.chunk_subseqs;
+        b.sd.stage = stage;
+        b.tab = view_of(s.table);
+        b.pair = s.table->pair ? 1 : 0;
+        b.pad = 0;
+        b.ntiles = ceil_div(si.n_subseq, 64);
+        b.item0 = items;
+        items += ceil_div(b.ntiles, wpg);
+        S_alloc = std::max(S_alloc, si.subseq_bits);
+        stage_alloc = std::max(stage_alloc, stage);
+        k1_alloc = std::max(k1_alloc, s.table->k1);
+        BatchScanStream &c = ss[i];
+        c.cc = s.chunk_counts;
+        c.off = reinterpret_cast<uint64_t *>(ws + L.off_at[i]);
+        c.M = si.n_chunks;
+        c.n = si.n_symbols;
+        c.blk0 = static_cast<uint32_t>(bl.size());
+        c.nblk = static_cast<uint32_t>(std::max<uint64_t>(1, ceil_div(si.n_chunks, kScanBlock)));
+        for (uint32_t k = 0; k < c.nblk; ++k)
+            bl.push_back({i, k});
+    }
+    // streams keep their own staging size; the launch reserves the largest
+    for (auto &b : d)
+        b.sd.stage = std::min(b.sd.stage, stage_alloc);
+    const uint32_t lds = table_lds_bytes(k1_alloc) + wpg * wave_area_bytes(S_alloc, stage_alloc);
+    if (lds + 64 > dev->lds_per_block)
+        return HD_ERR_UNSUPPORTED;
+
+    // upload descriptors through pinned staging
+    const size_t up = L.offs - L.desc;
+    StagingBuf *sb = staging_acquire(up);
+    if (!sb)
+        return HD_ERR_NOMEM;
+    char *h = static_cast<char *>(sb->host);
+    std::memset(h, 0, up);
+    std::memcpy(h + (L.desc - L.desc), d.data(), sizeof(BatchStreamDev) * n_streams);
+    std::memcpy(h + (L.sdesc - L.desc), ss.data(), sizeof(BatchScanStream) * n_streams);
+    std::memcpy(h + (L.blocks - L.desc), bl.data(), sizeof(BatchScanBlock) * bl.size());
+    if (hipMemcpyAsync(ws + L.desc, h, up, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipEventRecord(sb->done, stream) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        sb->busy = false;
+        return HD_ERR_DEVICE;
+    }
+    uint32_t *status = reinterpret_cast<uint32_t *>(ws);
+    unsigned long long *counter = reinterpret_cast<unsigned long long *>(ws + 64);
+    const BatchScanStream *ssd = reinterpret_cast<const BatchScanStream *>(ws + L.sdesc);
+    const BatchScanBlock *bld = reinterpret_cast<const BatchScanBlock *>(ws + L.blocks);
+    uint64_t *partial = reinterpret_cast<uint64_t *>(ws + L.partial);
+    hipLaunchKernelGGL(k_bscan_reduce, dim3(L.nblk_total), dim3(kScanThreads), 0, stream, ssd, bld, partial, status,
+                       counter);
+    hipLaunchKernelGGL(k_bscan_finish, dim3(L.nblk_total), dim3(kScanThreads), 0, stream, ssd, bld, partial, status);
+    if (hipGetLastError() != hipSuccess)
+        return HD_ERR_DEVICE;
+    BatchArgs a;
+    a.streams = reinterpret_cast<const BatchStreamDev *>(ws + L.desc);
+    a.n_streams = n_streams;
+    a.n_items = items;
+    a.counter = counter;
+    a.status = status;
+    a.S_alloc = S_alloc;
+    a.stage_alloc = stage_alloc;
+    a.k1_alloc = k1_alloc;
+    if (items == 0)
+        return HD_OK;
+    switch (wpg) {
+    case 4: return launch_batch<4>(a, lds, stream);
+    case 8: return launch_batch<8>(a, lds, stream);
+    default: return launch_batch<16>(a, lds, stream);
+    }
+}
+
+extern "C" hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *out, void *workspace,
+                                 size_t ws_bytes, void *hip_stream, hd_tune *best, float *best_ms)
+{
+    if (!best)
+        return HD_ERR_ARG;
+    hd_status st = check_call(sample, m, nullptr, workspace, ws_bytes);
+    if (st != HD_OK)
+        return st;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const uint32_t base = auto_stage_for(sample->info);
+    const double mult[] = {0.5, 0.75, 1.0, 1.5, 2.0};
+    const uint32_t wpgs[] = {4, 8, 16};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return HD_ERR_DEVICE;
+    float best_t = 0.f;
+    bool have = false;
+    // the output-index phase does not depend on the tune: run it once
+    st = hd_decode_prepare(sample, m, nullptr, workspace, ws_bytes, hip_stream);
+    for (uint32_t w : wpgs) {
+        for (double f : mult) {
+            if (st != HD_OK)
+                break;
+            uint32_t stage = static_cast<uint32_t>(base * f);
+            stage = std::min<uint32_t>(16384, std::max<uint32_t>(256, (stage + 63) / 64 * 64));
+            hd_tune t{w, stage, 0, 0};
+            Plan p;
+            if (make_plan(sample, &t, &p) != HD_OK)
+                continue;                               // LDS request too large
+            float times[3];
+            hd_status rs = hd_decode_run(sample, out, m, &t, workspace, ws_bytes, hip_stream);   // warm-up
+            for (int r = 0; r < 3 && rs == HD_OK; ++r) {
+                hipEventRecord(e0, stream);
+                rs = hd_decode_run(sample, out, m, &t, workspace, ws_bytes, hip_stream);
+                hipEventRecord(e1, stream);
+                if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&times[r], e0, e1) != hipSuccess)
+                    rs = HD_ERR_DEVICE;
+            }
+            if (rs != HD_OK) {
+                st = rs;
+                break;
+            }
+            std::sort(times, times + 3);
+            if (!have || times[1] < best_t) {
+                best_t = times[1];
+                *best = t;
+                have = true;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != HD_OK)
+        return st;
+    if (!have)
+        return HD_ERR_UNSUPPORTED;
+    if (best_ms)
+        *best_ms = best_t;
+    return HD_OK;
 }
 
 extern "C" uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream)

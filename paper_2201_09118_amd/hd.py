@@ -37,9 +37,19 @@ SIGNATURES = {
     "hd_decode_sync_points": (C.c_int, [_vp, _vp, _sz, _vp, _vp]),
     "hd_decode_batch_workspace_size": (C.c_int, [_vp, _u32, C.c_int, C.POINTER(_sz)]),
     "hd_decode_batch": (C.c_int, [_vp, _u32, _vp, C.c_int, _vp, _vp, _sz, _vp]),
+    "hd_autotune": (C.c_int, [_vp, C.c_int, _vp, _vp, _sz, _vp, _vp, _vp]),
     "hd_decode_status": (C.c_int, [_vp, _vp]),
     "hd_decode_status_bits": (_u32, [_vp, _vp]),
     "hd_status_str": (C.c_char_p, [C.c_int]),
+    "hd_server_create": (C.c_int, [_sz, _u32, _u32, C.POINTER(_vp)]),
+    "hd_server_destroy": (None, [_vp]),
+    "hd_server_submit": (C.c_int, [_vp, _vp, C.POINTER(_u64)]),
+    "hd_server_poll": (C.c_int, [_vp, _vp, _u32, C.POINTER(_u32)]),
+    "hd_server_result": (C.c_int, [_vp, _u64, C.POINTER(_vp), C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]),
+    "hd_server_release": (C.c_int, [_vp, _u64]),
+    "hd_server_stats": (C.c_int, [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
+                                  C.POINTER(_u64)]),
 }
 
 
@@ -287,14 +297,32 @@ def decode_batch_workspace_size(streams, mode: int = MODE_GAP) -> int:
     return int(n.value)
 
 
-def decode_batch(streams, outs, mode: int = MODE_GAP, tune=None, workspace=None, stream=None):
+def decode_batch(streams, outs, mode: int = MODE_GAP, tunes=None, workspace=None, stream=None):
+    """Enqueues hd_decode_batch; tunes is None or one Tune/dict per stream."""
     arr = (DStream * len(streams))(*[s.as_c() for s in streams])
     optrs = (C.c_void_p * len(outs))(*[o.data_ptr() if o.numel() else None for o in outs])
+    tptr = None
+    if tunes is not None:
+        ts = [t if isinstance(t, Tune) else Tune(t.get("waves_per_group", 0), t.get("stage_symbols", 0),
+                                                  t.get("groups_per_cu", 0), 0) for t in tunes]
+        tptr = (Tune * len(ts))(*ts)
     if workspace is None:
         workspace = alloc_workspace(decode_batch_workspace_size(streams, mode), outs[0].device)
-    _check(lib().hd_decode_batch(arr, len(streams), optrs, mode, _tune_ptr(tune), _dev_ptr(workspace),
+    _check(lib().hd_decode_batch(arr, len(streams), optrs, mode, tptr, _dev_ptr(workspace),
                                  workspace.numel(), _stream_handle(stream)), "hd_decode_batch")
     return workspace
+
+
+def autotune(ds: DeviceStream, out, workspace=None, mode: int = MODE_GAP, stream=None):
+    """hd_autotune on a sample stream -> (Tune, milliseconds of the fastest decode_run)."""
+    d = ds.as_c()
+    if workspace is None:
+        workspace = alloc_workspace(decode_workspace_size(ds, mode), out.device)
+    best = Tune()
+    ms = C.c_float()
+    _check(lib().hd_autotune(C.byref(d), mode, _dev_ptr(out), _dev_ptr(workspace), workspace.numel(),
+                             _stream_handle(stream), C.byref(best), C.byref(ms)), "hd_autotune")
+    return best, float(ms.value)
 
 
 def decode_status(workspace, stream=None) -> int:
@@ -303,3 +331,56 @@ def decode_status(workspace, stream=None) -> int:
 
 def decode_status_bits(workspace, stream=None) -> int:
     return int(lib().hd_decode_status_bits(_dev_ptr(workspace), _stream_handle(stream)))
+
+
+class Server:
+    """hd_server_*: continuous-batching decode server over an HBM budget."""
+
+    def __init__(self, hbm_budget: int, n_streams: int = 4, max_batch: int = 64):
+        self._h = C.c_void_p()
+        _check(lib().hd_server_create(hbm_budget, n_streams, max_batch, C.byref(self._h)), "hd_server_create")
+        self._keep = {}
+
+    def submit(self, ds: DeviceStream) -> int:
+        d = ds.as_c()
+        rid = C.c_uint64()
+        _check(lib().hd_server_submit(self._h, C.byref(d), C.byref(rid)), "hd_server_submit")
+        self._keep[rid.value] = ds          # buffers and table stay alive until completion
+        return rid.value
+
+    def poll(self, cap: int = 4096):
+        ids = (C.c_uint64 * cap)()
+        n = C.c_uint32()
+        _check(lib().hd_server_poll(self._h, ids, cap, C.byref(n)), "hd_server_poll")
+        return [ids[i] for i in range(n.value)]
+
+    def result(self, rid: int):
+        """(device pointer, status, t_submit, t_done) of a completed request."""
+        p = C.c_void_p()
+        st = C.c_int()
+        t0 = C.c_double()
+        t1 = C.c_double()
+        _check(lib().hd_server_result(self._h, rid, C.byref(p), C.byref(st), C.byref(t0), C.byref(t1)),
+               "hd_server_result")
+        return p.value, st.value, t0.value, t1.value
+
+    def release(self, rid: int):
+        _check(lib().hd_server_release(self._h, rid), "hd_server_release")
+        self._keep.pop(rid, None)
+
+    def stats(self):
+        v = [C.c_uint64() for _ in range(5)]
+        _check(lib().hd_server_stats(self._h, *[C.byref(x) for x in v]), "hd_server_stats")
+        return dict(zip(("batches", "done", "queued", "arena_used", "arena_peak"), (x.value for x in v)))
+
+    def close(self):
+        if self._h:
+            lib().hd_server_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
