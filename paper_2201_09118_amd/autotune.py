@@ -11,9 +11,10 @@ call (Table I).  Here tuning happens once per *stream class* and is cached:
   ``hd_autotune`` (a measured sweep in the library); the first-level table
   size (LDS table budget) is swept here by building tables of several widths.
 
-A class is (alphabet bucket, mean code length in half bits, S, log2 of the
-symbol count); results are keyed additionally by the GPU architecture and
-can be persisted as JSON.  Every measurement runs the library's kernels.
+A class is (alphabet bucket, mean code length in half bits, S); results are
+keyed additionally by the GPU architecture and can be persisted as JSON.
+Callers should tune a class on one of its larger streams (tiny streams are
+launch-bound and say little about the kernel).  Every measurement runs the library's kernels.
 """
 from __future__ import annotations
 
@@ -36,11 +37,11 @@ def _arch() -> str:
 
 
 def class_key(A: int, n_symbols: int, n_bits: int, S: int | None = None) -> str:
+    """Stream class: alphabet bucket, mean code length to half a bit, and S."""
     ab = next(b for b in ALPHABET_BUCKETS if A <= b) if A <= ALPHABET_BUCKETS[-1] else A
     lbar = n_bits / max(n_symbols, 1)
     lb = round(lbar * 2) / 2
-    nb = int(round(math.log2(max(n_symbols, 2)) / 2) * 2)
-    return f"A{ab}-l{lb:.1f}-n{nb}" + (f"-S{S}" if S else "")
+    return f"A{ab}-l{lb:.1f}" + (f"-S{S}" if S else "")
 
 
 class Autotuner:
@@ -98,7 +99,7 @@ class Autotuner:
         import torch
         xs = np.ascontiguousarray(x[:sample])
         bits = int(lengths[xs].astype(np.int64).sum())
-        key = self._key("layout-" + class_key(A, x.size, bits * x.size // max(xs.size, 1)))
+        key = self._key("layout-" + class_key(A, xs.size, bits))
         with self._mu:
             hit = self.cache.get(key)
         if hit:
