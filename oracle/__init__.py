@@ -52,6 +52,7 @@ def lib():
         L.hdref_encode.argtypes = [p, u64, p, p, u32, u32, u32, p, u64, p, u64, p, u64, p]
         L.hdref_decode.argtypes = [p, u64, u64, u64, p, p, u32, p]
         L.hdref_decode_prefix.argtypes = [p, u64, u64, u64, p, p, u32, p, p]
+        L.hdref_decode_from.argtypes = [p, u64, u64, u64, u64, p, p, u32, p, p]
         L.hdref_selfsync.argtypes = [p, u64, u64, u64, p, p, u32, u32, p, p, p]
         L.hdref_gap_backward.argtypes = [p, u64, u64, u64, p, p, u32, u32, p, p]
         for f in ("hdref_histogram", "hdref_code_lengths", "hdref_canonical_codes", "hdref_encode",
@@ -155,6 +156,47 @@ def decode_prefix(words, n_bits, n, lengths, codes, out=None):
     _check(lib().hdref_decode_prefix(_ptr(words), words.size, n_bits, n, _ptr(lengths), _ptr(codes),
                                      lengths.size, _ptr(out), _ptr(end)), "decode_prefix")
     return out, int(end[0])
+
+
+def decode_from(words, n_bits, start, n, lengths, codes, out=None):
+    """Decodes n symbols from codeword start `start` (no end check); returns (symbols, end bit)."""
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    codes = np.ascontiguousarray(codes, dtype=np.uint32)
+    if out is None:
+        out = np.zeros(n, dtype=np.uint16)
+    assert out.dtype == np.uint16 and out.flags.c_contiguous and out.size >= n
+    end = np.zeros(1, dtype=np.uint64)
+    _check(lib().hdref_decode_from(_ptr(words), words.size, n_bits, start, n, _ptr(lengths), _ptr(codes),
+                                   lengths.size, _ptr(out), _ptr(end)), "decode_from")
+    return out, int(end[0])
+
+
+def decode_chunks_parallel(words, n_bits, n, lengths, codes, gap, chunk_counts, S, C, threads):
+    """The bit-serial decoder run on `threads` host threads, one contiguous
+    range of chunks each, every range starting at its first subsequence's gap
+    entry.  Returns the decoded symbols."""
+    from concurrent.futures import ThreadPoolExecutor
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    codes = np.ascontiguousarray(codes, dtype=np.uint32)
+    out = np.zeros(n, dtype=np.uint16)
+    M = int(chunk_counts.size)
+    off = np.concatenate([[0], np.cumsum(chunk_counts.astype(np.uint64))]).astype(np.uint64)
+    bounds = [M * i // threads for i in range(threads + 1)]
+
+    def run(i):
+        c0, c1 = bounds[i], bounds[i + 1]
+        if c0 >= c1:
+            return
+        k0 = c0 * C
+        start = k0 * S + int(gap[k0])
+        o0, o1 = int(off[c0]), int(off[c1])
+        decode_from(words, n_bits, start, o1 - o0, lengths, codes, out[o0:o1])
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(run, range(threads)))
+    return out
 
 
 def selfsync(words, n_bits, n, lengths, codes, S):

@@ -27,6 +27,8 @@
  *   hdref_decode           bit-serial prefix-tree decoding, one bit at a time
  *                          (the behaviour of the baseline decoder, Sec. III-A),
  *                          for ANY prefix code, canonical or not.
+ *   hdref_decode_from      the same decoder started at a known codeword start
+ *                          (a gap-array entry), for chunk-parallel timing.
  *   hdref_selfsync         true synchronization points and per-subsequence
  *                          counts (Sec. III-B: one sync point per subsequence;
  *                          the count of valid codewords per subsequence feeds
@@ -492,6 +494,41 @@ int hdref_decode_prefix(const uint32_t *words, uint64_t n_words, uint64_t B, uin
         return rc;
     }
     uint64_t pos = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        int64_t s = tr_step(&t, words, &pos, B);
+        if (s < 0) {
+            free(t.nodes);
+            return HDREF_ECORRUPT;
+        }
+        out[i] = (uint16_t)s;
+    }
+    if (end_pos)
+        *end_pos = pos;
+    free(t.nodes);
+    return HDREF_OK;
+}
+
+/* Decodes n symbols starting at stream bit `start`, which must be a codeword
+ * start, without the end-of-stream check; the end position goes to *end_pos.
+ * Ranges of chunks are independent from their first subsequence's gap entry
+ * (start = k*S + gap[k]) and chunk counts (n), so a CPU baseline can run one
+ * call per range on every host core (Sec. III-C: the gap array lets each
+ * thread begin at a known codeword boundary). */
+int hdref_decode_from(const uint32_t *words, uint64_t n_words, uint64_t B, uint64_t start, uint64_t n,
+                      const uint8_t *len, const uint32_t *code, uint32_t A, uint16_t *out,
+                      uint64_t *end_pos)
+{
+    if (len == NULL || code == NULL || A == 0 || A > 65536 || (n > 0 && (out == NULL || words == NULL)))
+        return HDREF_EARG;
+    if (n_words * 32 < B || start > B)
+        return HDREF_EARG;
+    tr_tree t;
+    int rc = tr_build(&t, len, code, A);
+    if (rc != HDREF_OK) {
+        free(t.nodes);
+        return rc;
+    }
+    uint64_t pos = start;
     for (uint64_t i = 0; i < n; ++i) {
         int64_t s = tr_step(&t, words, &pos, B);
         if (s < 0) {

@@ -449,3 +449,34 @@ def test_fixed_length_code_never_resyncs_off_phase():
         else:
             assert sb[k] == UINT32_MAX
         assert sg[k] == (-32 * k) % 3
+
+
+@pytest.mark.parametrize("S,C", [(32, 1), (128, 32), (96, 3)])
+def test_decode_from_codeword_starts_matches_suffix(S, C):
+    """Started at any true codeword start (computed here by numpy from the
+    code lengths alone), the decoder reproduces the input's suffix and ends
+    on the codeword boundary after the last symbol."""
+    rng = np.random.default_rng(S + C)
+    x = (300 + np.rint(25 * rng.standard_normal(40000))).astype(np.uint16)
+    ln, cd = oracle.build_codebook(x, 1024, 20)
+    e = oracle.encode(x, ln, cd, S, C)
+    lens = ln[x].astype(np.int64)
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    for i in [0, 1, 17, 12345, x.size - 1]:
+        n = min(500, x.size - i)
+        got, end = oracle.decode_from(e.words, e.n_bits, int(starts[i]), n, ln, cd)
+        assert np.array_equal(got, x[i:i + n])
+        assert end == int(starts[i]) + int(lens[i:i + n].sum())
+    with pytest.raises(oracle.OracleError):
+        oracle.decode_from(e.words, e.n_bits, e.n_bits + 1, 1, ln, cd)
+
+
+@pytest.mark.parametrize("threads", [1, 5, 16])
+def test_chunk_parallel_decode_round_trips(threads):
+    rng = np.random.default_rng(threads)
+    x = (512 + rng.integers(-60, 61, 70001)).astype(np.uint16)
+    ln, cd = oracle.build_codebook(x, 1024, 16)
+    e = oracle.encode(x, ln, cd, 128, 32)
+    y = oracle.decode_chunks_parallel(e.words, e.n_bits, x.size, ln, cd, e.gap, e.chunk_counts, 128, 32,
+                                      threads)
+    assert np.array_equal(y, x)
