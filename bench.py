@@ -67,6 +67,17 @@ def workload(name):
     raise ValueError(name)
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,7 +99,11 @@ def main():
     ap.add_argument("--wpg", type=int, default=0)
     ap.add_argument("--stage", type=int, default=0)
     ap.add_argument("--groups-per-cu", type=int, default=0)
+    ap.add_argument("--cold-steps", type=int, default=5,
+                    help="extra steps, each after a 1 GiB scrub write (cold caches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="threads of the chunk-parallel CPU baseline (capped by the CPUs this process may use)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -134,6 +149,18 @@ def main():
                "sample": f"whole {args.workload} stream ({n} symbols), one pass of the bit-serial "
                          f"prefix-tree decoder on one core, {dt:.2f} s", "verified": ok}
         log(f"cpu oracle: {dt:.2f}s ({cpu['value']} GB/s), correct={ok}")
+        # the same decoder on every host core, one range of chunks per thread
+        # (each range starts at its first subsequence's gap entry)
+        threads = max(1, min(args.cpu_threads, len(os.sched_getaffinity(0))))
+        t0 = time.perf_counter()
+        y = oracle.decode_chunks_parallel(hs.words, B, n, ln, cd, hs.gap, hs.chunk_counts, S, Cc, threads)
+        dt = time.perf_counter() - t0
+        okp = bool(np.array_equal(y, x))
+        del y
+        cpu["all_cores"] = {"value": round(2.0 * n / dt / 1e9, 4), "unit": "GB/s", "cores": threads,
+                            "seconds": round(dt, 3), "verified": okp,
+                            "cpu": _cpu_model(), "host_cpus": os.cpu_count()}
+        log(f"cpu oracle on {threads} threads: {dt:.2f}s ({cpu['all_cores']['value']} GB/s), correct={okp}")
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -182,10 +209,42 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms_step = e0.elapsed_time(e1) / K_
-        k_avg = float(np.mean([a.elapsed_time(b) for a, b in zip(ev_a, ev_b)]))
+        k_all = [a.elapsed_time(b) for a, b in zip(ev_a, ev_b)]
+        k_avg = float(np.mean(k_all))
+        # per-step spread, and cold steps: a 1 GiB scrub write before each
+        # step evicts the L2s and the 256 MB last-level cache
+        steps_ms = []
+        for i in range(K_):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            hd.decode_prepare(ds, ws, mode, tune, stream)
+            hd.decode_run(ds, out, ws, mode, tune, stream)
+            b.record(stream)
+            steps_ms.append((a, b))
+        torch.cuda.synchronize()
+        steps_ms = [a.elapsed_time(b) for a, b in steps_ms]
+        scrub = torch.empty(1 << 29, dtype=torch.int16, device=dev)
+        cold_ms = []
+        for i in range(args.cold_steps):
+            scrub.fill_(i)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            hd.decode_prepare(ds, ws, mode, tune, stream)
+            hd.decode_run(ds, out, ws, mode, tune, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            cold_ms.append(a.elapsed_time(b))
+        del scrub
+        pct = lambda v, q: round(float(np.percentile(v, q)), 5) if len(v) else None
         res[mname] = dict(ms_step=ms_step, k_ms=k_avg, verified=verified,
-                          value=2.0 * n / (ms_step * 1e-3) / 1e9)
-        log(f"{mname}: {ms_step:.4f} ms/step ({res[mname]['value']:.1f} GB/s), decode kernel {k_avg:.4f} ms")
+                          value=2.0 * n / (ms_step * 1e-3) / 1e9,
+                          warm={"median_ms": pct(steps_ms, 50), "p10_ms": pct(steps_ms, 10),
+                                "p90_ms": pct(steps_ms, 90), "decode_run_median_ms": pct(k_all, 50)},
+                          cold={"steps": len(cold_ms), "median_ms": pct(cold_ms, 50), "p10_ms": pct(cold_ms, 10),
+                                "p90_ms": pct(cold_ms, 90),
+                                "gbs": round(2.0 * n / (np.median(cold_ms) * 1e-3) / 1e9, 2) if cold_ms else None})
+        log(f"{mname}: {ms_step:.4f} ms/step ({res[mname]['value']:.1f} GB/s), decode kernel {k_avg:.4f} ms; "
+            f"warm {res[mname]['warm']}, cold {res[mname]['cold']}")
         del ds, ws
 
     head = res[modes[0]]
@@ -220,7 +279,7 @@ def main():
         "verified": all(r["verified"] for r in res.values()),
         "modes": {m: {"value": round(r["value"], 2), "ms_per_step": round(r["ms_step"], 5),
                       "decode_run_ms": round(r["k_ms"], 5), "prepare_ms": round(r["ms_step"] - r["k_ms"], 5),
-                      "verified": r["verified"]} for m, r in res.items()},
+                      "warm": r["warm"], "cold": r["cold"], "verified": r["verified"]} for m, r in res.items()},
     }
     verified = rec["verified"]
     print(json.dumps(rec), flush=True)
@@ -292,13 +351,14 @@ def bench_batch(args):
     xs, books, layouts, hss = _prepare_streams(specs, tuner)
     n_tot = sum(x.size for x in xs)
     # tuned tables + per-stream decode params (autotuner), and default tables for the plain baseline
-    tuned, tunes, plain = [], [], []
+    tuned, tunes, plain, k1s = [], [], [], []
     for i in sorted(range(len(xs)), key=lambda i: -xs[i].size):   # tune each class on its largest stream
         tuner.decode_params(books[i][0], books[i][1], 24, hss[i], specs[i]["A"])
     for x, sp, (ln, cd), hs in zip(xs, specs, books, hss):
         k1, tn = tuner.decode_params(ln, cd, 24, hs, sp["A"])
         tuned.append(hd.DeviceStream.from_host(hs, hd.Table(ln, cd, 24, k1), device=dev))
         tunes.append(tn)
+        k1s.append(k1)
         plain.append(hd.DeviceStream.from_host(hs, hd.Table(ln, cd, 24), device=dev))
     log(f"autotuner classes: {len(tuner.cache)}")
     outs = [torch.empty(max(x.size, 8), dtype=torch.int16, device=dev) for x in xs]
@@ -309,8 +369,13 @@ def bench_batch(args):
         for d, o, w in zip(plain, outs, wss):
             hd.decode(d, o, hd.MODE_GAP, None, w)
 
+    classes = [autotune.class_key(sp["A"], hs.n_symbols, hs.n_bits, int(hs.info.subseq_bits))
+               for sp, hs in zip(specs, hss)]
+    btunes, shape_ms = tuner.batch_launch(tuned, outs, tunes, bws, classes)
+    log(f"batch launch shapes (ms): {shape_ms}")
+
     def run_batch():
-        hd.decode_batch(tuned, outs, hd.MODE_GAP, tunes, bws)
+        hd.decode_batch(tuned, outs, hd.MODE_GAP, btunes, bws)
 
     ok = True
     for name, fn, ws in (("plain", run_plain, wss[0]), ("batched", run_batch, bws)):
@@ -325,6 +390,10 @@ def bench_batch(args):
     t_plain = _time_ms(run_plain, args.steps)
     t_batch = _time_ms(run_batch, args.steps)
     log(f"plain back-to-back {t_plain:.3f} ms, batched {t_batch:.3f} ms")
+    mix = {}
+    for t, k1 in zip(tunes, k1s):
+        key = f"k1={k1} wpg={t.waves_per_group} stage={t.stage_symbols}"
+        mix[key] = mix.get(key, 0) + 1
     g_plain = 2.0 * n_tot / (t_plain * 1e-3) / 1e9
     g_batch = 2.0 * n_tot / (t_batch * 1e-3) / 1e9
     rec = {
@@ -336,7 +405,11 @@ def bench_batch(args):
                    "sizes": [args.batch_lo, args.batch_hi], "alphabets": [256, 1024, 4096], "max_len": 24},
         "batched_speedup": round(t_plain / t_batch, 3),
         "plain_back_to_back": {"ms": round(t_plain, 4), "gbs": round(g_plain, 2)},
-        "batched": {"ms": round(t_batch, 4), "gbs": round(g_batch, 2)},
+        "batched": {"ms": round(t_batch, 4), "gbs": round(g_batch, 2), "launches": 1,
+                    "shape": {"waves_per_group": btunes[0].waves_per_group or "occupancy",
+                              "stage_cap": max(t.stage_symbols for t in btunes)}},
+        "launch_shape_sweep_ms": shape_ms,
+        "tune_mix": mix,
         "autotuner_classes": len(tuner.cache), "layouts": [list(v) for v in sorted(set(layouts))],
         "verified": bool(ok),
     }

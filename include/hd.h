@@ -91,7 +91,8 @@ typedef struct hd_table hd_table;
 
 /* Decode-time knobs.  Zero in any field means "choose automatically". */
 typedef struct {
-    uint32_t waves_per_group; /* wavefronts per workgroup: 4, 8 or 16             */
+    uint32_t waves_per_group; /* wavefronts per workgroup, 1..16 (automatic: the
+                                 most wavefronts per CU the LDS footprint allows) */
     uint32_t stage_symbols;   /* LDS output staging per wavefront, in symbols,
                                  a multiple of 64 in [256, 16384]                 */
     uint32_t groups_per_cu;   /* persistent workgroups per compute unit           */
@@ -231,14 +232,17 @@ hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, uint32_t n_s
  * aligned) with one segmented chunk-offset scan and one persistent decode
  * launch.  The paper groups sequences by compression ratio and launches one
  * kernel per group, each with its own shared-memory size (Sec. IV-C, Alg. 2);
- * here workgroups pull (stream, group of tiles) items from one counter and
- * reload the LDS decode table only when the stream changes.  per_stream, when
- * not NULL, holds n_streams tunes: stage_symbols per stream (the launch
- * reserves the largest) and waves_per_group of per_stream[0] for the launch.
- * m must be HD_MODE_GAP (HD_ERR_UNSUPPORTED otherwise).  Per-call
- * descriptors are uploaded through library-owned pinned staging, without a
- * host wait.  Asynchronous on hip_stream; the status word (hd_decode_status)
- * covers every stream of the batch.
+ * here workgroups walk (stream, group of tiles) items of every stream and
+ * reload the LDS decode table only when the stream changes.  The launch's LDS
+ * layout reserves the largest table, subsequence and staging of the batch.
+ * per_stream, when not NULL, holds n_streams tunes: stage_symbols of each
+ * stream (0: from its mean code length), and the launch's waves_per_group and
+ * groups_per_cu from per_stream[0] (0: the most resident wavefronts the
+ * layout allows).  m must be HD_MODE_GAP (HD_ERR_UNSUPPORTED otherwise);
+ * HD_ERR_UNSUPPORTED also when the layout exceeds a workgroup's LDS.
+ * Per-call descriptors are uploaded through library-owned pinned staging,
+ * without a host wait.  Asynchronous on hip_stream; the status word
+ * (hd_decode_status) covers every stream of the batch.
  */
 hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_streams, uint16_t *const *outs,
                           hd_mode m, const hd_tune *per_stream, void *workspace, size_t ws_bytes,
@@ -250,9 +254,9 @@ hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_streams, uint16_
  * (Sec. IV-C, Alg. 2, Table I) and compares against a brute-force sweep;
  * here the sweep itself is the tuner, run once per stream class and cached
  * by the caller: hd_decode_run is timed with HIP events (median of three
- * after a warm-up) for waves_per_group in {4, 8, 16} times staging sizes of
- * 0.5x .. 2x the expected tile output, and the fastest tune goes to *best
- * (its time to *best_ms when not NULL).  out and workspace are as for
+ * after a warm-up) for waves_per_group in {the occupancy choice, 4, 8, 16}
+ * times staging sizes of 0.5x .. 2x the expected tile output, and the fastest
+ * tune goes to *best (its time to *best_ms when not NULL).  out and workspace are as for
  * hd_decode on this sample (their contents are overwritten).  Synchronous:
  * waits for hip_stream.
  */

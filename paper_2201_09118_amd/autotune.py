@@ -9,7 +9,9 @@ call (Table I).  Here tuning happens once per *stream class* and is cached:
   tuned decode (time per symbol);
 * decode time: waves per workgroup and LDS staging size come from
   ``hd_autotune`` (a measured sweep in the library); the first-level table
-  size (LDS table budget) is swept here by building tables of several widths.
+  size (LDS table budget) is swept here by building tables of several widths;
+* batched launch: the one launch's waves per workgroup and staging cap are
+  measured on the batch itself (per set of classes).
 
 A class is (alphabet bucket, mean code length in half bits, S); results are
 keyed additionally by the GPU architecture and can be persisted as JSON.
@@ -90,6 +92,53 @@ class Autotuner:
             self.cache[key] = {"lut_bits": int(k1), "wpg": int(wpg), "stage": int(stage), "ms": ms,
                                "n": hs.n_symbols}
         return k1, hd.Tune(wpg, stage, 0, 0)
+
+    # -- batch launch shape ----------------------------------------------------
+
+    def batch_launch(self, streams, outs, tunes, workspace, class_keys, reps: int = 3):
+        """Shape of one batched launch, measured on this batch: waves per
+        workgroup (0 = the library's occupancy choice) times a cap on the
+        staging the launch reserves (streams above the cap decode in passes).
+        Returns (per-stream tunes with the chosen shape, {option: ms})."""
+        import torch
+        key = self._key("batch-" + ",".join(sorted(set(class_keys))))
+        smax = max(t.stage_symbols for t in tunes)
+        with self._mu:
+            hit = self.cache.get(key)
+
+        def shaped(w, cap):
+            return [hd.Tune(w if i == 0 else 0, min(t.stage_symbols, cap), 0, 0) for i, t in enumerate(tunes)]
+
+        if hit:
+            return shaped(hit["wpg"], hit["stage_cap"]), hit["options"]
+        options = {}
+        best = None
+        for f in (1.0, 0.75, 0.5):
+            cap = max(256, int(smax * f) // 64 * 64)
+            for w in (0, 4, 8, 12, 16):
+                tu = shaped(w, cap)
+                try:
+                    hd.decode_batch(streams, outs, hd.MODE_GAP, tu, workspace)
+                except hd.HDError:
+                    continue                      # layout above a workgroup's LDS
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(reps):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    hd.decode_batch(streams, outs, hd.MODE_GAP, tu, workspace)
+                    b.record()
+                    torch.cuda.synchronize()
+                    ts.append(a.elapsed_time(b))
+                ms = float(np.median(ts))
+                options[f"wpg{w}-cap{cap}"] = round(ms, 4)
+                if best is None or ms < best[0]:
+                    best = (ms, w, cap)
+        if best is None:
+            raise RuntimeError("no batch launch shape fits")
+        with self._mu:
+            self.cache[key] = {"wpg": best[1], "stage_cap": best[2], "ms": best[0], "options": options}
+        return shaped(best[1], best[2]), options
 
     # -- encode-time layout --------------------------------------------------
 

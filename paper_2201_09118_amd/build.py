@@ -28,13 +28,15 @@ def build(verbose: bool = False) -> str:
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
     for src in SOURCES:
         obj = os.path.join(tmpdir, src + ".o")
-        cmd = [hipcc()] + common + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc()] + common
         if src == "hd_serve.cpp":
             cmd += ["-pthread"]
         if src.endswith(".hip"):
-            cmd += ["-x", "hip", f"--offload-arch={ARCH}",
-                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                    "-fgpu-rdc" if False else "-fno-gpu-rdc", "-munsafe-fp-atomics"]
+            # packed fp32 instructions stay off: the kernels are integer work
+            # and some packed fp32 forms are not trusted on this target
+            cmd += [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                    "-fno-gpu-rdc", "-munsafe-fp-atomics", "-x", "hip"]
+        cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

@@ -224,7 +224,10 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
         t->base_off = t->lim_off + 33 * 8;
         t->syms_off = align_up(t->base_off + 33 * 8, 16);
         t->bytes = align_up(t->syms_off + 2 * syms.size(), 256);
-        hipGetDevice(&t->device);
+        if (hipGetDevice(&t->device) != hipSuccess) {
+            delete t;
+            return HD_ERR_DEVICE;
+        }
         std::vector<unsigned char> img(t->bytes, 0);
         std::memcpy(img.data() + t->lut_off, lut.data(), 4 * nlut);
         std::memcpy(img.data() + t->lim_off, lim.data(), 33 * 8);
@@ -240,7 +243,7 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
         if (hipMemcpyAsync(t->image, img.data(), t->bytes, hipMemcpyHostToDevice, stream) !=
                 hipSuccess ||
             hipStreamSynchronize(stream) != hipSuccess) {
-            hipFree(t->image);
+            (void)hipFree(t->image);
             delete t;
             return HD_ERR_DEVICE;
         }
@@ -256,8 +259,8 @@ extern "C" void hd_table_destroy(hd_table *t)
     if (!t)
         return;
     if (t->image) {
-        hipDeviceSynchronize();
-        hipFree(t->image);
+        (void)hipDeviceSynchronize();     // no decode may still read the table
+        (void)hipFree(t->image);
     }
     delete t;
 }
@@ -400,6 +403,80 @@ __device__ __forceinline__ void lookup(const uint32_t *TTl, uint32_t q, const Sm
     }
 }
 
+// Length a and count n of the codewords a first-level entry covers (one, or
+// up to two in pair format); false for a slow entry (first codeword longer
+// than k1, or no codeword at all).
+template <bool PAIR>
+__device__ __forceinline__ bool entry_group(uint32_t e, uint32_t k1, uint32_t &a, uint32_t &n)
+{
+    if (PAIR) {
+        const uint32_t l1 = (e >> 24) & 0xfu, l2 = e >> 28;
+        a = l1 + l2;
+        n = 1 + (l2 != 0);
+        return e >= (1u << 24);
+    }
+    a = e >> 16;
+    n = 1;
+    return a - 1u < k1;
+}
+
+// Slow first group of a window: one codeword through the per-length limits.
+__device__ __forceinline__ uint32_t slow_group(uint32_t v, const SmemTable &st, const TableView &g,
+                                               uint32_t &a, uint32_t &n, uint32_t &err)
+{
+    uint32_t l;
+    const uint32_t s = decode_long(v, g.k1, g.L, st.lim, st.base, g.syms, &l);
+    if (l == 0) {
+        err |= kErrBadCode;
+        l = 1;
+    }
+    a = l;
+    n = 1;
+    return s;
+}
+
+// Walks from q (bit position + 31) over every codeword that starts before
+// qe and returns their count; q is left on the first start at or after qe.
+// Two table lookups per window read: after a fast group (<= k1 <= 14 bits)
+// the 32-bit window still holds at least k1 unread bits.  A group is taken
+// while all its codewords surely start before the end (group start + k1 <=
+// qe); the last few codewords go one lookup at a time, and a pair's second
+// codeword that starts at or past the end is given back.
+template <bool PAIR>
+__device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q, uint32_t qe,
+                                               const SmemTable &st, const TableView &g, uint32_t sh,
+                                               uint32_t &err)
+{
+    const uint32_t k1 = g.k1;
+    uint32_t cnt = 0;
+    while (q + k1 <= qe) {
+        const uint32_t v = window_at(TTl, q);
+        uint32_t a1, n1, a2, n2;
+        const bool fast1 = entry_group<PAIR>(st.lut[v >> sh], k1, a1, n1);
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
+            if (!fast1)
+                slow_group(v, st, g, a1, n1, err);
+        }
+        const bool fast2 = entry_group<PAIR>(st.lut[(v << (a1 & 31u)) >> sh], k1, a2, n2);
+        const bool take2 = fast1 && fast2 && q + a1 + k1 <= qe;
+        q += a1 + (take2 ? a2 : 0u);
+        cnt += n1 + (take2 ? n2 : 0u);
+    }
+    uint32_t qm = q, l2 = 0;
+    while (q < qe) {
+        uint32_t s1, s2, l1;
+        lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
+        qm = q + l1;
+        q = qm + l2;
+        cnt += 1 + (l2 != 0);
+    }
+    if (PAIR && l2 != 0 && qm >= qe) {
+        --cnt;
+        q = qm;
+    }
+    return cnt;
+}
+
 // ------------------------------------------------------------------------
 // Output-index scan over chunks (Sec. III-B, step 3)
 // ------------------------------------------------------------------------
@@ -529,29 +606,36 @@ struct TileIn {
     uint32_t pwn = 0, gk = 0, gn = 0;
     uint64_t c_lo = 0, c_hi = 0;
 
+    // Units of subsequence k (k < K) and the next subsequence's first unit
+    // ((k+1)*S/32 < n_words for k < K).
+    __device__ __forceinline__ void load_words(const uint32_t *words, uint64_t k, uint32_t wps)
+    {
+        const uint32_t *src = words + k * wps;
+        if ((wps & 3) == 0) {
+#pragma unroll
+            for (uint32_t i = 0; i < kMaxUnitsPerLane / 4; ++i)
+                if (4 * i < wps) {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(src + 4 * i);
+                    pw[4 * i] = v.x;
+                    pw[4 * i + 1] = v.y;
+                    pw[4 * i + 2] = v.z;
+                    pw[4 * i + 3] = v.w;
+                }
+        } else {
+#pragma unroll
+            for (uint32_t i = 0; i < kMaxUnitsPerLane; ++i)
+                if (i < wps)
+                    pw[i] = src[i];
+        }
+        pwn = src[wps];
+    }
+
     __device__ __forceinline__ void load(const StreamDev &sd, uint64_t t, uint64_t ntiles, int lane)
     {
         const uint32_t wps = sd.S >> 5;
         const uint64_t k = (t << 6) + lane;
         if (t < ntiles && k < sd.K) {
-            const uint32_t *src = sd.words + k * wps;
-            if ((wps & 3) == 0) {
-#pragma unroll
-                for (uint32_t i = 0; i < kMaxUnitsPerLane / 4; ++i)
-                    if (4 * i < wps) {
-                        const uint4 v = *reinterpret_cast<const uint4 *>(src + 4 * i);
-                        pw[4 * i] = v.x;
-                        pw[4 * i + 1] = v.y;
-                        pw[4 * i + 2] = v.z;
-                        pw[4 * i + 3] = v.w;
-                    }
-            } else {
-#pragma unroll
-                for (uint32_t i = 0; i < kMaxUnitsPerLane; ++i)
-                    if (i < wps)
-                        pw[i] = src[i];
-            }
-            pwn = src[wps];                           // (k+1)*S/32 < n_words for k < K
+            load_words(sd.words, k, wps);
             gk = sd.gap[k];
             gn = k + 1 < sd.K ? sd.gap[k + 1] : 0u;
             c_lo = sd.chunk_off[k / sd.C];             // bounds of this lane's chunk
@@ -599,24 +683,9 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
     if (rs > re)
         rs = re;
     const uint32_t qe = re + 31;
-    uint32_t cnt = 0;
+    const uint32_t k1 = g.k1;
     uint32_t q = rs + 31;
-    {
-        // both codewords of a pair are taken; a second codeword that starts
-        // at or past the end is given back after the loop
-        uint32_t qm = q, l2 = 0;
-        while (q < qe) {
-            uint32_t s1, s2, l1;
-            lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
-            qm = q + l1;
-            q = qm + l2;
-            cnt += 1 + (l2 != 0);
-        }
-        if (PAIR && l2 != 0 && qm >= qe) {
-            --cnt;
-            q = qm;
-        }
-    }
+    const uint32_t cnt = count_walk<PAIR>(TTl, q, qe, st, g, sh, err);
     // the walk must stop exactly on the next subsequence's start
     if (act) {
         const uint32_t expect = (k + 1 < sd.K) ? S + gn : re;
@@ -648,6 +717,30 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
         const uint32_t jmax = lim_rel > excl ? min(cnt, lim_rel - excl) : 0u;
         // dst index of symbol j: a0 + excl + j - pb (>= a0 whenever j < jmax)
         uint16_t *dst = stage + (static_cast<int32_t>(a0 + excl) - static_cast<int32_t>(pb));
+        // two lookups per window read while at least two full groups remain
+        // in this pass; untaken slots are rewritten by later symbols of the lane
+        while (j + (PAIR ? 4u : 2u) <= jmax) {
+            const uint32_t v = window_at(TTl, q);
+            const uint32_t e1 = st.lut[v >> sh];
+            uint32_t a1, n1, a2, n2;
+            const bool fast1 = entry_group<PAIR>(e1, k1, a1, n1);
+            uint32_t s1 = PAIR ? (e1 & 0xfffu) : (e1 & 0xffffu);
+            if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
+                if (!fast1)
+                    s1 = slow_group(v, st, g, a1, n1, err);
+            }
+            dst[j] = static_cast<uint16_t>(s1);
+            if (PAIR)
+                dst[j + 1] = static_cast<uint16_t>((e1 >> 12) & 0xfffu);
+            j += n1;
+            const uint32_t e2 = st.lut[(v << (a1 & 31u)) >> sh];
+            const bool take2 = entry_group<PAIR>(e2, k1, a2, n2) && fast1;
+            dst[j] = static_cast<uint16_t>(PAIR ? (e2 & 0xfffu) : (e2 & 0xffffu));
+            if (PAIR)
+                dst[j + 1] = static_cast<uint16_t>((e2 >> 12) & 0xfffu);
+            j += take2 ? n2 : 0u;
+            q += a1 + (take2 ? a2 : 0u);
+        }
         while (j < jmax) {
             uint32_t s1, s2, l1, l2;
             lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
@@ -688,8 +781,8 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
     }
 }
 
-template <int WPG, bool PAIR>
-__global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
+template <bool PAIR>
+__global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const TableView &g = a.tab;
@@ -709,11 +802,12 @@ __global__ __launch_bounds__(WPG * 64) void k_decode_gap(GapArgs a)
 
     uint32_t err = 0;
     const uint64_t ntiles = (sd.K + 63) >> 6;
-    const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * WPG;
+    const uint32_t wpg = blockDim.x >> 6;
+    const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * wpg;
     // Tile inputs travel through registers one tile ahead: while tile t is
     // decoded, the inputs of the wavefront's next tile are in flight.
     TileIn in;
-    uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv;
+    uint64_t t = static_cast<uint64_t>(blockIdx.x) * wpg + wv;
     in.load(sd, t, ntiles, lane);
     for (; t < ntiles; t += tstride) {
         const bool act = (t << 6) + lane < sd.K;
@@ -777,40 +871,22 @@ struct SyncArgs {
     uint32_t S;
 };
 
-template <bool PAIR>
-__device__ __forceinline__ uint32_t codeword_len(const uint32_t *TTc, uint32_t r, const SmemTable &st,
-                                                 const TableView &g, uint32_t sh)
-{
-    uint32_t s1, s2, l1, l2, e = 0;
-    lookup<PAIR>(TTc, r + 31, st, g, sh, s1, s2, l1, l2, e);
-    return l1;
-}
-
 // Path from relative bit r: codewords starting before E, and the first start
 // at or after E (exit).
 template <bool PAIR>
 __device__ __forceinline__ void run_path(const uint32_t *TTc, uint32_t r, uint32_t E, const SmemTable &st,
                                          const TableView &g, uint32_t sh, uint32_t &exit, uint32_t &cnt)
 {
-    uint32_t q = r + 31, qm = q, l2 = 0, e = 0;
-    const uint32_t qe = E + 31;
-    cnt = 0;
-    while (q < qe) {
-        uint32_t s1, s2, l1;
-        lookup<PAIR>(TTc, q, st, g, sh, s1, s2, l1, l2, e);
-        qm = q + l1;
-        q = qm + l2;
-        cnt += 1 + (l2 != 0);
-    }
-    if (PAIR && l2 != 0 && qm >= qe) {
-        --cnt;
-        q = qm;
-    }
+    uint32_t q = r + 31, e = 0;
+    cnt = count_walk<PAIR>(TTc, q, E + 31, st, g, sh, e);
     exit = q - 31;
 }
 
 // New path from `in` against the old path (st0, ex0, cn0): advance whichever
-// position is behind until they meet or the new one reaches E.
+// position is behind until they meet or the new one reaches E.  A pair
+// entry advances two codewords at once when the first one lands strictly
+// before the other path (and, for the new path, before E): the one-codeword
+// walk would then take the second codeword next anyway.
 template <bool PAIR>
 __device__ __forceinline__ void walk_merge(const uint32_t *TTc, uint32_t in, uint32_t st0, uint32_t ex0,
                                            uint32_t cn0, uint32_t E, const SmemTable &st,
@@ -828,13 +904,18 @@ __device__ __forceinline__ void walk_merge(const uint32_t *TTc, uint32_t in, uin
             cn = na;
             return;
         }
-        const uint32_t len = codeword_len<PAIR>(TTc, min(a, b), st, g, sh);
-        if (a < b) {
-            a += len;
-            ++na;
+        const bool adv_a = a < b;
+        const uint32_t p = adv_a ? a : b;
+        uint32_t s1, s2, l1, l2, e = 0;
+        lookup<PAIR>(TTc, p + 31, st, g, sh, s1, s2, l1, l2, e);
+        const bool two = PAIR && l2 != 0 && p + l1 < (adv_a ? min(b, E) : a);
+        const uint32_t d = l1 + (two ? l2 : 0u), dn = 1u + (two ? 1u : 0u);
+        if (adv_a) {
+            a += d;
+            na += dn;
         } else {
-            b += len;
-            ++nb;
+            b += d;
+            nb += dn;
         }
     }
 }
@@ -945,9 +1026,17 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_sync(SyncArgs a)
     const uint32_t wps = a.S >> 5;
     uint32_t *TTl = reinterpret_cast<uint32_t *>(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S)) + lane;
     const uint32_t sh = 32 - g.k1;
-    for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv; t < a.ntiles;
-         t += static_cast<uint64_t>(gridDim.x) * WPG) {
-        load_units(TTl, a.words, (t << 6) + lane, a.K, wps);
+    const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * WPG;
+    // the next tile's units travel through registers while this one syncs
+    TileIn in;
+    uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv;
+    if (t < a.ntiles && (t << 6) + lane < a.K)
+        in.load_words(a.words, (t << 6) + lane, wps);
+    for (; t < a.ntiles; t += tstride) {
+        in.store_units(TTl, wps, (t << 6) + lane < a.K);
+        const uint64_t tn = t + tstride;
+        if (tn < a.ntiles && (tn << 6) + lane < a.K)
+            in.load_words(a.words, (tn << 6) + lane, wps);
         wave_lds_sync();
         sync_and_store<PAIR>(a, t, TTl, lane, 0u, true, st, g, sh);
         wave_lds_sync();
@@ -998,16 +1087,21 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
 // The paper groups sequences by compression ratio and launches one decode
 // kernel per group, each with its own shared-memory size, on separate
 // streams (Sec. IV-C, Alg. 2).  Here one persistent launch covers every
-// stream of a batch: a work item is a group of WPG consecutive wavefront
-// tiles of one stream (items never straddle streams), items are numbered
-// stream by stream, and each workgroup pulls items from an atomic counter,
-// reloading the decode table into LDS only when its next item belongs to
-// another stream.  Per-stream chunk offsets come from one segmented scan.
+// stream of a batch, its LDS layout reserving the largest table, subsequence
+// and staging of the batch.  A work item is WPG consecutive wavefront tiles
+// of one stream (items never straddle streams); items are numbered stream by
+// stream and workgroup b takes items b, b + grid, b + 2 grid, ...  The item
+// sequence of a workgroup is fixed, so every wave of it knows when the next
+// item belongs to another stream: only then do the waves meet at a barrier
+// while the stream's table is loaded into LDS.  Otherwise waves run on their
+// own, with the next item's tile inputs in registers while the current tile
+// decodes, as in the single-stream kernel.  Per-stream chunk offsets come
+// from one segmented scan over the batch.
 
 struct BatchStreamDev {
     StreamDev sd;
     TableView tab;
-    uint64_t item0;       // first work item of this stream
+    uint64_t item0;       // first work item of this stream (within its launch)
     uint64_t ntiles;
     uint32_t pair;
     uint32_t pad;
@@ -1017,17 +1111,27 @@ struct BatchArgs {
     const BatchStreamDev *streams;
     uint32_t n_streams;
     uint64_t n_items;
-    unsigned long long *counter;
     uint32_t *status;
     uint32_t S_alloc, stage_alloc, k1_alloc;
 };
 
-template <int WPG>
-__global__ __launch_bounds__(WPG * 64) void k_decode_batch(BatchArgs a)
+// Last stream at or after `from` whose first item is <= item (empty streams
+// share their successor's item0 and are stepped over).
+__device__ __forceinline__ uint32_t batch_stream_of(const BatchArgs &a, uint64_t item, uint32_t from)
+{
+    uint32_t s = from;
+    while (s + 1 < a.n_streams && a.streams[s + 1].item0 <= item)
+        ++s;
+    return s;
+}
+
+// Table formats a batch launch must handle: all pair, all one-symbol, or both.
+constexpr int kBatchPairOnly = 0, kBatchWideOnly = 1, kBatchMixed = 2;
+
+template <int FORMATS>
+__global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __shared__ unsigned long long s_item;
-    __shared__ uint32_t s_stream;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     unsigned char *area = smem + table_lds_bytes(a.k1_alloc) + wv * wave_area_bytes(a.S_alloc, a.stage_alloc);
@@ -1035,49 +1139,45 @@ __global__ __launch_bounds__(WPG * 64) void k_decode_batch(BatchArgs a)
     uint16_t *stage = reinterpret_cast<uint16_t *>(area + wave_units_bytes(a.S_alloc));
     uint16_t *dummy = stage + a.stage_alloc + lane;
     uint32_t err = 0;
+    const uint32_t wpg = blockDim.x >> 6;
+    const uint64_t istride = gridDim.x;
+    uint64_t item = blockIdx.x;
+    uint32_t si = batch_stream_of(a, item, 0);
     uint32_t cur = 0xffffffffu;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            const unsigned long long item = atomicAdd(a.counter, 1ull);
-            uint32_t lo = 0, hi = a.n_streams;          // last stream with item0 <= item
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (a.streams[mid].item0 <= item)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            s_item = item;
-            s_stream = lo;
-        }
-        __syncthreads();
-        const unsigned long long item = s_item;
-        const uint32_t si = s_stream;
-        if (item >= a.n_items)
-            break;
+    TileIn in;
+    if (item < a.n_items) {
+        const BatchStreamDev &b0 = a.streams[si];
+        in.load(b0.sd, (item - b0.item0) * wpg + wv, b0.ntiles, lane);
+    }
+    for (; item < a.n_items; item += istride) {
         const BatchStreamDev &bs = a.streams[si];
-        const SmemTable st = carve_table(smem, bs.tab.k1);
         if (si != cur) {
-            load_table(st, bs.tab);
+            __syncthreads();                 // every wave is done with the previous table
+            load_table(carve_table(smem, bs.tab.k1), bs.tab);
+            __syncthreads();
             cur = si;
         }
-        __syncthreads();
-        const uint64_t t = (item - bs.item0) * WPG + wv;
-        if (t < bs.ntiles) {
-            const bool act = (t << 6) + lane < bs.sd.K;
-            TileIn in;
-            in.load(bs.sd, t, bs.ntiles, lane);
-            in.store_units(TTl, bs.sd.S >> 5, act);
-            wave_lds_sync();
-            const uint32_t sh = 32 - bs.tab.k1;
-            if (bs.pair)
-                decode_tile<true>(bs.sd, t, lane, in.gk, in.gn, in.c_lo, in.c_hi, TTl, stage, dummy, st,
-                                  bs.tab, sh, err);
-            else
-                decode_tile<false>(bs.sd, t, lane, in.gk, in.gn, in.c_lo, in.c_hi, TTl, stage, dummy, st,
-                                   bs.tab, sh, err);
+        const uint64_t t = (item - bs.item0) * wpg + wv;
+        const bool live = t < bs.ntiles;
+        in.store_units(TTl, bs.sd.S >> 5, live && (t << 6) + lane < bs.sd.K);
+        const uint32_t gk = in.gk, gn = in.gn;
+        const uint64_t c_lo = in.c_lo, c_hi = in.c_hi;
+        const uint64_t nitem = item + istride;
+        const uint32_t nsi = nitem < a.n_items ? batch_stream_of(a, nitem, si) : si;
+        if (nitem < a.n_items) {
+            const BatchStreamDev &nb = a.streams[nsi];
+            in.load(nb.sd, (nitem - nb.item0) * wpg + wv, nb.ntiles, lane);
         }
-        __syncthreads();        // the table may change with the next item
+        wave_lds_sync();
+        if (live) {
+            const SmemTable st = carve_table(smem, bs.tab.k1);
+            const uint32_t sh = 32 - bs.tab.k1;
+            if (FORMATS == kBatchPairOnly || (FORMATS == kBatchMixed && bs.pair))
+                decode_tile<true>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, bs.tab, sh, err);
+            else
+                decode_tile<false>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, bs.tab, sh, err);
+        }
+        si = nsi;
     }
     if (err)
         atomicOr(a.status, err);
@@ -1096,14 +1196,11 @@ struct BatchScanBlock {
 };
 
 __global__ __launch_bounds__(kScanThreads) void k_bscan_reduce(const BatchScanStream *ss, const BatchScanBlock *bl,
-                                                               uint64_t *partial, uint32_t *status,
-                                                               unsigned long long *counter)
+                                                               uint64_t *partial, uint32_t *status)
 {
     __shared__ uint64_t sh[kScanThreads / 64];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0)
         *status = 0;
-        *counter = 0;
-    }
     const BatchScanBlock b = bl[blockIdx.x];
     const BatchScanStream st = ss[b.stream];
     const uint64_t b0 = static_cast<uint64_t>(b.blk) * kScanBlock;
@@ -1168,6 +1265,9 @@ namespace {
 
 constexpr size_t kWsHeader = 256;          // status word + padding
 
+constexpr uint32_t kMaxWavesPerGroup = 16;    // 1024 work-items
+constexpr uint32_t kMaxWavesPerCu = 32;       // 8 wavefronts per SIMD
+
 struct Plan {
     uint32_t wpg, stage, groups_per_cu;
     uint32_t lds_bytes;
@@ -1218,23 +1318,46 @@ uint32_t auto_stage_for(const hd_stream_info &si)
     return std::min<uint32_t>(8192, std::max<uint32_t>(512, (st + 255) / 256 * 256));
 }
 
+// Wavefronts per workgroup with the most resident wavefronts per CU for a
+// workgroup LDS footprint of table + wpg * area (ties: the smaller
+// workgroup).  The table is shared by a workgroup's wavefronts, so larger
+// workgroups amortize it; the LDS of a CU is what bounds residency.
+uint32_t occupancy_wpg(uint32_t table, uint32_t area, const DeviceInfo *dev)
+{
+    uint32_t best = 0, best_waves = 0;
+    for (uint32_t w = 1; w <= kMaxWavesPerGroup; ++w) {
+        const uint64_t lds = table + uint64_t(w) * area;
+        if (lds > dev->lds_per_block)
+            break;
+        const uint32_t fit = std::min<uint32_t>(static_cast<uint32_t>(dev->lds_per_cu / lds), kMaxWavesPerCu / w);
+        if (fit * w > best_waves) {
+            best = w;
+            best_waves = fit * w;
+        }
+    }
+    return best;
+}
+
 hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
 {
     const DeviceInfo *dev = device_info();
     if (!dev)
         return HD_ERR_DEVICE;
-    p->wpg = tune && tune->waves_per_group ? tune->waves_per_group : 4;
     p->stage = tune && tune->stage_symbols ? tune->stage_symbols : auto_stage_for(s->info);
-    if (p->wpg != 4 && p->wpg != 8 && p->wpg != 16)
-        return HD_ERR_ARG;
     if (p->stage < 256 || p->stage > 16384 || p->stage % 64)
         return HD_ERR_ARG;
     const uint32_t S = s->info.subseq_bits;
-    p->lds_bytes = table_lds_bytes(s->table->k1) + p->wpg * wave_area_bytes(S, p->stage);
+    const uint32_t table = table_lds_bytes(s->table->k1), area = wave_area_bytes(S, p->stage);
+    p->wpg = tune && tune->waves_per_group ? tune->waves_per_group : occupancy_wpg(table, area, dev);
+    if (p->wpg == 0)
+        return HD_ERR_UNSUPPORTED;                   // not even one wavefront fits
+    if (p->wpg > kMaxWavesPerGroup)
+        return HD_ERR_ARG;
+    p->lds_bytes = table + p->wpg * area;
     if (p->lds_bytes > dev->lds_per_block)
         return HD_ERR_UNSUPPORTED;
     uint32_t fit = static_cast<uint32_t>(dev->lds_per_cu / p->lds_bytes);
-    fit = std::max<uint32_t>(1, std::min<uint32_t>(fit, 32 / p->wpg));
+    fit = std::max<uint32_t>(1, std::min<uint32_t>(fit, kMaxWavesPerCu / p->wpg));
     p->groups_per_cu = tune && tune->groups_per_cu ? std::min(tune->groups_per_cu, fit) : fit;
     const uint64_t ntiles = ceil_div(s->info.n_subseq, 64);
     const uint64_t want = ceil_div(ntiles, p->wpg);
@@ -1326,18 +1449,18 @@ hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, h
                           : launch_sync<kWpg, false>(a, grid, lds, stream);
 }
 
-template <int WPG, bool PAIR>
+template <bool PAIR>
 hd_status launch_gap(const GapArgs &a, const Plan &p, hipStream_t stream)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_gap<WPG, PAIR>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_gap<PAIR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 static_cast<int>(device_info()->lds_per_block)) != hipSuccess)
             return HD_ERR_DEVICE;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_decode_gap<WPG, PAIR>), dim3(p.grid), dim3(WPG * 64), p.lds_bytes, stream, a);
+    hipLaunchKernelGGL((k_decode_gap<PAIR>), dim3(p.grid), dim3(p.wpg * 64), p.lds_bytes, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
 
@@ -1466,18 +1589,7 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     a.sd.stage = p.stage;
     a.status = w.status;
     a.tab = view_of(s->table);
-    if (s->table->pair) {
-        switch (p.wpg) {
-        case 4: return launch_gap<4, true>(a, p, stream);
-        case 8: return launch_gap<8, true>(a, p, stream);
-        default: return launch_gap<16, true>(a, p, stream);
-        }
-    }
-    switch (p.wpg) {
-    case 4: return launch_gap<4, false>(a, p, stream);
-    case 8: return launch_gap<8, false>(a, p, stream);
-    default: return launch_gap<16, false>(a, p, stream);
-    }
+    return s->table->pair ? launch_gap<true>(a, p, stream) : launch_gap<false>(a, p, stream);
 }
 
 extern "C" hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
@@ -1513,7 +1625,7 @@ extern "C" hd_status hd_decode_sync_points(const hd_dstream *s, const void *work
 
 namespace {
 
-// Workspace layout of a batch: header (status, item counter), stream
+// Workspace layout of a batch: header (status word), stream
 // descriptors, scan descriptors, scan block list, scan partials, then every
 // stream's chunk offsets.
 struct BatchLayout {
@@ -1585,24 +1697,31 @@ StagingBuf *staging_acquire(size_t bytes)
     return b;
 }
 
-template <int WPG>
-hd_status launch_batch(const BatchArgs &a, uint32_t lds, hipStream_t stream)
+template <int FORMATS>
+hd_status launch_batch_as(const BatchArgs &a, uint32_t wpg, uint32_t lds, uint32_t grid, hipStream_t stream)
 {
     static bool attr_set = false;
-    const DeviceInfo *dev = device_info();
     if (!attr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_batch<WPG>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_batch<FORMATS>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                static_cast<int>(dev->lds_per_block) - 64) != hipSuccess)
+                                static_cast<int>(device_info()->lds_per_block)) != hipSuccess)
             return HD_ERR_DEVICE;
         attr_set = true;
     }
-    uint32_t fit = static_cast<uint32_t>(dev->lds_per_cu / (lds + 64));
-    fit = std::max<uint32_t>(1, std::min<uint32_t>(fit, 32 / WPG));
-    const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(a.n_items, uint64_t(dev->cus) * fit)));
-    hipLaunchKernelGGL(k_decode_batch<WPG>, dim3(grid), dim3(WPG * 64), lds, stream, a);
+    hipLaunchKernelGGL(k_decode_batch<FORMATS>, dim3(grid), dim3(wpg * 64), lds, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
+
+hd_status launch_batch(const BatchArgs &a, int formats, uint32_t wpg, uint32_t lds, uint32_t grid,
+                       hipStream_t stream)
+{
+    switch (formats) {
+    case kBatchPairOnly: return launch_batch_as<kBatchPairOnly>(a, wpg, lds, grid, stream);
+    case kBatchWideOnly: return launch_batch_as<kBatchWideOnly>(a, wpg, lds, grid, stream);
+    default: return launch_batch_as<kBatchMixed>(a, wpg, lds, grid, stream);
+    }
+}
+
 
 }  // namespace
 
@@ -1650,10 +1769,43 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
     char *ws = static_cast<char *>(workspace);
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
 
-    const uint32_t wpg = per_stream && per_stream[0].waves_per_group ? per_stream[0].waves_per_group : 4;
-    if (wpg != 4 && wpg != 8 && wpg != 16)
+    // one launch for the whole batch: the LDS layout reserves the largest
+    // table, subsequence and staging of the batch; waves per workgroup and
+    // workgroups per CU come from per_stream[0] (zero: the most resident
+    // wavefronts that layout allows)
+    uint32_t S_alloc = 32, stage_alloc = 256, k1_alloc = 1, n_pair = 0;
+    std::vector<uint32_t> stage(n_streams);
+    for (uint32_t i = 0; i < n_streams; ++i) {
+        const hd_stream_info &si = streams[i].info;
+        const hd_tune *tu = per_stream ? &per_stream[i] : nullptr;
+        stage[i] = tu && tu->stage_symbols ? tu->stage_symbols : auto_stage_for(si);
+        if (stage[i] < 256 || stage[i] > 16384 || stage[i] % 64)
+            return HD_ERR_ARG;
+        if ((si.n_symbols && !outs[i]) || reinterpret_cast<uintptr_t>(outs[i]) % 16 ||
+            reinterpret_cast<uintptr_t>(streams[i].words) % 16)
+            return HD_ERR_ARG;
+        if (64 % si.chunk_subseqs)
+            return HD_ERR_UNSUPPORTED;
+        S_alloc = std::max(S_alloc, si.subseq_bits);
+        stage_alloc = std::max(stage_alloc, stage[i]);
+        k1_alloc = std::max(k1_alloc, streams[i].table->k1);
+        n_pair += streams[i].table->pair ? 1u : 0u;
+    }
+    const uint32_t table = table_lds_bytes(k1_alloc), area = wave_area_bytes(S_alloc, stage_alloc);
+    const hd_tune *t0 = per_stream ? &per_stream[0] : nullptr;
+    const uint32_t wpg = t0 && t0->waves_per_group ? t0->waves_per_group : occupancy_wpg(table, area, dev);
+    if (wpg == 0)
+        return HD_ERR_UNSUPPORTED;
+    if (wpg > kMaxWavesPerGroup)
         return HD_ERR_ARG;
-    uint32_t S_alloc = 32, stage_alloc = 256, k1_alloc = 1;
+    const uint32_t lds = table + wpg * area;
+    if (lds > dev->lds_per_block)
+        return HD_ERR_UNSUPPORTED;
+    uint32_t fit = std::max<uint32_t>(1, std::min<uint32_t>(static_cast<uint32_t>(dev->lds_per_cu / lds),
+                                                            kMaxWavesPerCu / wpg));
+    if (t0 && t0->groups_per_cu)
+        fit = std::min(fit, t0->groups_per_cu);
+
     std::vector<BatchStreamDev> d(n_streams);
     std::vector<BatchScanStream> ss(n_streams);
     std::vector<BatchScanBlock> bl;
@@ -1662,14 +1814,6 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
     for (uint32_t i = 0; i < n_streams; ++i) {
         const hd_dstream &s = streams[i];
         const hd_stream_info &si = s.info;
-        if ((si.n_symbols && !outs[i]) || reinterpret_cast<uintptr_t>(outs[i]) % 16 ||
-            reinterpret_cast<uintptr_t>(s.words) % 16)
-            return HD_ERR_ARG;
-        if (64 % si.chunk_subseqs)
-            return HD_ERR_UNSUPPORTED;
-        uint32_t stage = per_stream && per_stream[i].stage_symbols ? per_stream[i].stage_symbols : auto_stage_for(si);
-        if (stage < 256 || stage > 16384 || stage % 64)
-            return HD_ERR_ARG;
         BatchStreamDev &b = d[i];
         b.sd.words = s.words;
         b.sd.gap = s.gap;
@@ -1682,16 +1826,13 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
         b.sd.n_words = si.n_words;
         b.sd.S = si.subseq_bits;
         b.sd.C = si.chunk_subseqs;
-        b.sd.stage = stage;
+        b.sd.stage = stage[i];
         b.tab = view_of(s.table);
         b.pair = s.table->pair ? 1 : 0;
         b.pad = 0;
         b.ntiles = ceil_div(si.n_subseq, 64);
         b.item0 = items;
         items += ceil_div(b.ntiles, wpg);
-        S_alloc = std::max(S_alloc, si.subseq_bits);
-        stage_alloc = std::max(stage_alloc, stage);
-        k1_alloc = std::max(k1_alloc, s.table->k1);
         BatchScanStream &c = ss[i];
         c.cc = s.chunk_counts;
         c.off = reinterpret_cast<uint64_t *>(ws + L.off_at[i]);
@@ -1702,12 +1843,6 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
         for (uint32_t k = 0; k < c.nblk; ++k)
             bl.push_back({i, k});
     }
-    // streams keep their own staging size; the launch reserves the largest
-    for (auto &b : d)
-        b.sd.stage = std::min(b.sd.stage, stage_alloc);
-    const uint32_t lds = table_lds_bytes(k1_alloc) + wpg * wave_area_bytes(S_alloc, stage_alloc);
-    if (lds + 64 > dev->lds_per_block)
-        return HD_ERR_UNSUPPORTED;
 
     // upload descriptors through pinned staging
     const size_t up = L.offs - L.desc;
@@ -1726,31 +1861,26 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
         return HD_ERR_DEVICE;
     }
     uint32_t *status = reinterpret_cast<uint32_t *>(ws);
-    unsigned long long *counter = reinterpret_cast<unsigned long long *>(ws + 64);
     const BatchScanStream *ssd = reinterpret_cast<const BatchScanStream *>(ws + L.sdesc);
     const BatchScanBlock *bld = reinterpret_cast<const BatchScanBlock *>(ws + L.blocks);
     uint64_t *partial = reinterpret_cast<uint64_t *>(ws + L.partial);
-    hipLaunchKernelGGL(k_bscan_reduce, dim3(L.nblk_total), dim3(kScanThreads), 0, stream, ssd, bld, partial, status,
-                       counter);
+    hipLaunchKernelGGL(k_bscan_reduce, dim3(L.nblk_total), dim3(kScanThreads), 0, stream, ssd, bld, partial, status);
     hipLaunchKernelGGL(k_bscan_finish, dim3(L.nblk_total), dim3(kScanThreads), 0, stream, ssd, bld, partial, status);
     if (hipGetLastError() != hipSuccess)
         return HD_ERR_DEVICE;
+    if (items == 0)
+        return HD_OK;
     BatchArgs a;
     a.streams = reinterpret_cast<const BatchStreamDev *>(ws + L.desc);
     a.n_streams = n_streams;
     a.n_items = items;
-    a.counter = counter;
     a.status = status;
     a.S_alloc = S_alloc;
     a.stage_alloc = stage_alloc;
     a.k1_alloc = k1_alloc;
-    if (items == 0)
-        return HD_OK;
-    switch (wpg) {
-    case 4: return launch_batch<4>(a, lds, stream);
-    case 8: return launch_batch<8>(a, lds, stream);
-    default: return launch_batch<16>(a, lds, stream);
-    }
+    const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(items, uint64_t(dev->cus) * fit)));
+    const int formats = n_pair == n_streams ? kBatchPairOnly : n_pair == 0 ? kBatchWideOnly : kBatchMixed;
+    return launch_batch(a, formats, wpg, lds, grid, stream);
 }
 
 extern "C" hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *out, void *workspace,
@@ -1764,7 +1894,7 @@ extern "C" hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const uint32_t base = auto_stage_for(sample->info);
     const double mult[] = {0.5, 0.75, 1.0, 1.5, 2.0};
-    const uint32_t wpgs[] = {4, 8, 16};
+    const uint32_t wpgs[] = {0, 4, 8, 16};     // 0: the occupancy choice for each staging size
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return HD_ERR_DEVICE;
@@ -1782,12 +1912,21 @@ extern "C" hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *
             Plan p;
             if (make_plan(sample, &t, &p) != HD_OK)
                 continue;                               // LDS request too large
+            if (w == 0 && (p.wpg == 4 || p.wpg == 8 || p.wpg == 16))
+                continue;                               // timed with the fixed sizes
+            t.waves_per_group = p.wpg;
             float times[3];
             hd_status rs = hd_decode_run(sample, out, m, &t, workspace, ws_bytes, hip_stream);   // warm-up
             for (int r = 0; r < 3 && rs == HD_OK; ++r) {
-                hipEventRecord(e0, stream);
+                if (hipEventRecord(e0, stream) != hipSuccess) {
+                    rs = HD_ERR_DEVICE;
+                    break;
+                }
                 rs = hd_decode_run(sample, out, m, &t, workspace, ws_bytes, hip_stream);
-                hipEventRecord(e1, stream);
+                if (rs == HD_OK && hipEventRecord(e1, stream) != hipSuccess)
+                    rs = HD_ERR_DEVICE;
+                if (rs != HD_OK)
+                    break;
                 if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&times[r], e0, e1) != hipSuccess)
                     rs = HD_ERR_DEVICE;
             }
@@ -1803,8 +1942,8 @@ extern "C" hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != HD_OK)
         return st;
     if (!have)

@@ -218,9 +218,15 @@ void hd_server::launch_locked()
             if (ids.empty())
                 return;
         }
-        const hd_status st = hd_decode_batch(ds.data(), static_cast<uint32_t>(ds.size()), outs.data(),
-                                             HD_MODE_GAP, nullptr, static_cast<char *>(base) + ws_off, wsb,
-                                             streams[slot]);
+        hd_status st = hd_decode_batch(ds.data(), static_cast<uint32_t>(ds.size()), outs.data(), HD_MODE_GAP,
+                                       nullptr, static_cast<char *>(base) + ws_off, wsb, streams[slot]);
+        // the batch's status word travels to pinned memory behind the decode
+        if (st == HD_OK && (hipMemcpyAsync(&status_host[slot], static_cast<char *>(base) + ws_off, sizeof(uint32_t),
+                                           hipMemcpyDeviceToHost, streams[slot]) != hipSuccess ||
+                            hipEventRecord(events[slot], streams[slot]) != hipSuccess)) {
+            (void)hipStreamSynchronize(streams[slot]);    // the decode may still use the workspace
+            st = HD_ERR_DEVICE;
+        }
         const double t = now_s();
         if (st != HD_OK) {
             for (uint64_t id : ids) {
@@ -234,9 +240,6 @@ void hd_server::launch_locked()
             arena->release(ws_off);
             continue;
         }
-        hipMemcpyAsync(&status_host[slot], static_cast<char *>(base) + ws_off, sizeof(uint32_t),
-                       hipMemcpyDeviceToHost, streams[slot]);
-        hipEventRecord(events[slot], streams[slot]);
         Batch bt;
         bt.ids = ids;
         bt.ws_off = ws_off;
@@ -255,7 +258,7 @@ void hd_server::launch_locked()
 
 void hd_server::loop()
 {
-    hipSetDevice(device);
+    (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     while (!stop || !running.empty()) {
         retire_locked();
@@ -282,7 +285,10 @@ extern "C" hd_status hd_server_create(size_t hbm_budget, uint32_t n_hip_streams,
     hd_server *s = new (std::nothrow) hd_server();
     if (!s)
         return HD_ERR_NOMEM;
-    hipGetDevice(&s->device);
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return HD_ERR_DEVICE;
+    }
     s->max_batch = max_batch;
     if (hipMalloc(&s->base, hbm_budget) != hipSuccess) {
         delete s;
@@ -291,7 +297,7 @@ extern "C" hd_status hd_server_create(size_t hbm_budget, uint32_t n_hip_streams,
     s->arena = new Arena(hbm_budget);
     if (hipHostMalloc(reinterpret_cast<void **>(&s->status_host), sizeof(uint32_t) * n_hip_streams,
                       hipHostMallocDefault) != hipSuccess) {
-        hipFree(s->base);
+        (void)hipFree(s->base);
         delete s->arena;
         delete s;
         return HD_ERR_NOMEM;
@@ -302,9 +308,11 @@ extern "C" hd_status hd_server_create(size_t hbm_budget, uint32_t n_hip_streams,
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
             for (auto x : s->streams)
-                hipStreamDestroy(x);
-            hipHostFree(s->status_host);
-            hipFree(s->base);
+                (void)hipStreamDestroy(x);
+            for (auto x : s->events)
+                (void)hipEventDestroy(x);
+            (void)hipHostFree(s->status_host);
+            (void)hipFree(s->base);
             delete s->arena;
             delete s;
             return HD_ERR_DEVICE;
@@ -330,13 +338,13 @@ extern "C" void hd_server_destroy(hd_server *s)
     if (s->worker.joinable())
         s->worker.join();
     for (auto st : s->streams) {
-        hipStreamSynchronize(st);
-        hipStreamDestroy(st);
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
     }
     for (auto ev : s->events)
-        hipEventDestroy(ev);
-    hipHostFree(s->status_host);
-    hipFree(s->base);
+        (void)hipEventDestroy(ev);
+    (void)hipHostFree(s->status_host);
+    (void)hipFree(s->base);
     delete s->arena;
     delete s;
 }

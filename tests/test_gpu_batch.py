@@ -72,6 +72,22 @@ def test_batch_equals_single_decodes_and_tunes():
             assert np.array_equal(g, expected(c))
 
 
+@pytest.mark.parametrize("shape", [(0, 0), (4, 1), (8, 2), (12, 0)])
+def test_batch_staging_and_launch_shapes(shape):
+    """Per-stream staging sizes (several multi-pass) in one launch whose waves
+    per workgroup and workgroups per CU come from the first tune (0: the
+    occupancy choice); tiny streams interleaved with large ones."""
+    cases = _mixed_cases(45, 18, 1, 400_000)
+    rng = np.random.default_rng(2)
+    tunes = [{"stage_symbols": int(rng.choice([256, 512, 2048]))} for _ in cases]
+    tunes[0].update(waves_per_group=shape[0], groups_per_cu=shape[1])
+    flush(f"batch with launch shape {shape}")
+    dss, got, bits = _run_batch(cases, tunes)
+    assert bits == 0, f"status {bits:#x}"
+    for c, g in zip(cases, got):
+        assert np.array_equal(g, expected(c))
+
+
 def test_batch_reports_corrupt_stream():
     from paper_2201_09118_amd import hd
     cases = _mixed_cases(43, 4, 10_000, 50_000)
@@ -109,3 +125,27 @@ def test_config4_shaped_batch_small():
     assert bits == 0
     for c, g in zip(cases, got):
         assert np.array_equal(g, expected(c))
+
+
+def test_autotuned_batch_launch_shape_decodes_exactly():
+    import torch
+    from paper_2201_09118_amd import autotune, hd
+    specs = hdsynth.batch_stream_specs(n_streams=12, lo=1 << 10, hi=1 << 17)
+    cases = [make_case(hdsynth.batch_stream_symbols(sp), sp["A"], 24, 64, 64) for sp in specs]
+    dss = [upload(c) for c in cases]
+    outs = [torch.full((max(c.x.size, 8),), -1, dtype=torch.int16, device="cuda") for c in cases]
+    ws = hd.alloc_workspace(hd.decode_batch_workspace_size(dss))
+    tuner = autotune.Autotuner()
+    tunes = [hd.Tune(0, 1024, 0, 0) for _ in cases]
+    keys = [autotune.class_key(sp["A"], c.x.size, c.enc.n_bits, 64) for sp, c in zip(specs, cases)]
+    flush("batch launch autotune")
+    shaped, options = tuner.batch_launch(dss, outs, tunes, ws, keys, reps=1)
+    assert options and len(shaped) == len(cases)
+    for o in outs:
+        o.fill_(-1)
+    hd.decode_batch(dss, outs, hd.MODE_GAP, shaped, ws)
+    assert hd.decode_status_bits(ws) == 0
+    for c, o in zip(cases, outs):
+        assert np.array_equal(o[:c.x.size].cpu().numpy().view(np.uint16), expected(c))
+    again, _ = tuner.batch_launch(dss, outs, tunes, ws, keys)       # cached
+    assert [t.waves_per_group for t in again] == [t.waves_per_group for t in shaped]

@@ -133,7 +133,7 @@ def test_last_subsequence_without_codeword_start():
     _check(case)
 
 
-@pytest.mark.parametrize("wpg", [4, 8, 16])
+@pytest.mark.parametrize("wpg", [0, 1, 4, 6, 8, 12, 16])
 def test_tune_variants(wpg):
     x = hdsynth.two_sided_geometric(np.random.default_rng(5), 700_000, 0.5, 1024)
     case = make_case(x, 1024, 24, 128, 32)
@@ -149,6 +149,15 @@ def test_tune_variants(wpg):
             except hd.HDError as err:          # LDS request above the per-workgroup limit
                 assert err.status == hd.ERR_UNSUPPORTED
     assert ran >= 2
+
+
+def test_wave_count_out_of_range_is_rejected():
+    from paper_2201_09118_amd import hd
+    x = hdsynth.two_sided_geometric(np.random.default_rng(7), 10_000, 0.5, 1024)
+    ds = upload(make_case(x, 1024, 24, 128, 32))
+    with pytest.raises(hd.HDError) as ei:
+        run_decode(ds, tune={"waves_per_group": 17})
+    assert ei.value.status == hd.ERR_ARG
 
 
 def test_deterministic_repeat():
