@@ -883,10 +883,9 @@ __device__ __forceinline__ void run_path(const uint32_t *TTc, uint32_t r, uint32
 }
 
 // New path from `in` against the old path (st0, ex0, cn0): advance whichever
-// position is behind until they meet or the new one reaches E.  A pair
-// entry advances two codewords at once when the first one lands strictly
-// before the other path (and, for the new path, before E): the one-codeword
-// walk would then take the second codeword next anyway.
+// position is behind, one codeword at a time, until they meet or the new one
+// reaches E.  (Two-codeword steps from pair entries were measured slower here:
+// these walks are short and the extra selects outweigh the saved lookups.)
 template <bool PAIR>
 __device__ __forceinline__ void walk_merge(const uint32_t *TTc, uint32_t in, uint32_t st0, uint32_t ex0,
                                            uint32_t cn0, uint32_t E, const SmemTable &st,
@@ -904,18 +903,14 @@ __device__ __forceinline__ void walk_merge(const uint32_t *TTc, uint32_t in, uin
             cn = na;
             return;
         }
-        const bool adv_a = a < b;
-        const uint32_t p = adv_a ? a : b;
         uint32_t s1, s2, l1, l2, e = 0;
-        lookup<PAIR>(TTc, p + 31, st, g, sh, s1, s2, l1, l2, e);
-        const bool two = PAIR && l2 != 0 && p + l1 < (adv_a ? min(b, E) : a);
-        const uint32_t d = l1 + (two ? l2 : 0u), dn = 1u + (two ? 1u : 0u);
-        if (adv_a) {
-            a += d;
-            na += dn;
+        lookup<PAIR>(TTc, min(a, b) + 31, st, g, sh, s1, s2, l1, l2, e);
+        if (a < b) {
+            a += l1;
+            ++na;
         } else {
-            b += d;
-            nb += dn;
+            b += l1;
+            ++nb;
         }
     }
 }
@@ -1027,16 +1022,9 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_sync(SyncArgs a)
     uint32_t *TTl = reinterpret_cast<uint32_t *>(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S)) + lane;
     const uint32_t sh = 32 - g.k1;
     const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * WPG;
-    // the next tile's units travel through registers while this one syncs
-    TileIn in;
-    uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv;
-    if (t < a.ntiles && (t << 6) + lane < a.K)
-        in.load_words(a.words, (t << 6) + lane, wps);
-    for (; t < a.ntiles; t += tstride) {
-        in.store_units(TTl, wps, (t << 6) + lane < a.K);
-        const uint64_t tn = t + tstride;
-        if (tn < a.ntiles && (tn << 6) + lane < a.K)
-            in.load_words(a.words, (tn << 6) + lane, wps);
+    // (loading the next tile's units one tile ahead measured no faster here)
+    for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv; t < a.ntiles; t += tstride) {
+        load_units(TTl, a.words, (t << 6) + lane, a.K, wps);
         wave_lds_sync();
         sync_and_store<PAIR>(a, t, TTl, lane, 0u, true, st, g, sh);
         wave_lds_sync();
