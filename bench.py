@@ -92,9 +92,11 @@ def main():
     ap.add_argument("--serve-lo", type=int, default=1 << 20)
     ap.add_argument("--serve-hi", type=int, default=1 << 28)
     ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000")
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
-    ap.add_argument("--serve-min-requests", type=int, default=100)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-min-requests", type=int, default=1000)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-streams", type=int, default=4, help="HIP streams of the server")
+    ap.add_argument("--serve-max-batch", type=int, default=16, help="requests per batch at most")
     ap.add_argument("--lut-bits", type=int, default=0)
     ap.add_argument("--wpg", type=int, default=0)
     ap.add_argument("--stage", type=int, default=0)
@@ -433,11 +435,11 @@ def bench_serve(args):
     log(f"pool: {len(pool)} streams, {sum(x.size for x in xs)} symbols, tables cached {len(cache)}")
     outs = [torch.empty(max(x.size, 8), dtype=torch.int16, device=dev) for x in xs]
     wss = [hd.alloc_workspace(hd.decode_workspace_size(d), dev) for d in pool]
-    server = hd.Server(int(args.serve_budget_gb * 1e9), n_streams=4, max_batch=64)
+    server = hd.Server(int(args.serve_budget_gb * 1e9), n_streams=args.serve_streams, max_batch=args.serve_max_batch)
     bad = []
 
     def check(i, ptr, n, which=None):
-        if i % 97 == 0 and not np.array_equal(serve.copy_from_device(ptr, n), xs[which[i]]):
+        if not np.array_equal(serve.copy_from_device(ptr, n), xs[which[i]]):
             bad.append(i)
 
     rates = [float(r) for r in args.serve_rates.split(",")]
@@ -445,7 +447,8 @@ def bench_serve(args):
     for rate in rates:
         nreq = max(args.serve_min_requests, int(rate * args.serve_seconds))
         times, which = serve.poisson_schedule(rate, nreq, len(pool), seed=int(rate))
-        srv = serve.run_served(server, pool, times, which, lambda i, p, n: check(i, p, n, which))
+        srv = serve.run_served(server, pool, times, which, lambda i, p, n: check(i, p, n, which),
+                               check_every=max(97, nreq // 64))
         ser = serve.run_serial(pool, times, which, outs, wss)
         per_rate.append({"rate": rate, "requests": nreq,
                          "served": {"gbs": round(srv["gbs"], 2), "p50_ms": round(srv["p50_ms"], 3),
@@ -454,7 +457,7 @@ def bench_serve(args):
                                     "p99_ms": round(ser["p99_ms"], 3)}})
         log(f"rate {rate}/s: served {per_rate[-1]['served']} serial {per_rate[-1]['serial']}")
     times, which = serve.burst_schedule(256, len(pool))
-    srv = serve.run_served(server, pool, times, which, lambda i, p, n: check(i, p, n, which))
+    srv = serve.run_served(server, pool, times, which, lambda i, p, n: check(i, p, n, which), check_every=97)
     ser = serve.run_serial(pool, times, which, outs, wss)
     stats = server.stats()
     server.close()
@@ -471,6 +474,7 @@ def bench_serve(args):
         "dtype": "u16", "data": "synthetic",
         "config": {"workload": "serve", "pool_streams": len(pool), "sizes": [args.serve_lo, args.serve_hi],
                    "alphabets": [1024, 4096], "budget_gb": args.serve_budget_gb, "rates": rates,
+                   "hip_streams": args.serve_streams, "max_batch": args.serve_max_batch,
                    "seconds_per_rate": args.serve_seconds},
         "p50_ms": top["served"]["p50_ms"], "p99_ms": top["served"]["p99_ms"],
         "per_rate": per_rate, "burst": burst, "server_stats": stats,

@@ -236,9 +236,12 @@ hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, uint32_t n_s
  * reload the LDS decode table only when the stream changes.  The launch's LDS
  * layout reserves the largest table, subsequence and staging of the batch.
  * per_stream, when not NULL, holds n_streams tunes: stage_symbols of each
- * stream (0: from its mean code length), and the launch's waves_per_group and
- * groups_per_cu from per_stream[0] (0: the most resident wavefronts the
- * layout allows).  m must be HD_MODE_GAP (HD_ERR_UNSUPPORTED otherwise);
+ * stream, and the launch's waves_per_group and groups_per_cu from
+ * per_stream[0] (0: the most resident wavefronts the layout allows).  A zero
+ * (or absent) stage_symbols takes the stream's need from its mean code length,
+ * capped for the batch at the larger of the staging that keeps 16 wavefronts
+ * resident per CU and the symbol-weighted median need; tiles above the cap
+ * are written in passes.  m must be HD_MODE_GAP (HD_ERR_UNSUPPORTED otherwise);
  * HD_ERR_UNSUPPORTED also when the layout exceeds a workgroup's LDS.
  * Per-call descriptors are uploaded through library-owned pinned staging,
  * without a host wait.  Asynchronous on hip_stream; the status word

@@ -835,9 +835,13 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 //
 // Step 1 (intra-tile): every lane first decodes from its raw boundary (lane
 // 0 from the tile's entry).  Then, in rounds, each lane takes its
-// predecessor's exit as its start; a lane whose start changed walks the new
-// path in lockstep with the old one until they meet (the exit stays, the
-// count is re-derived) or the new path leaves the subsequence (a new exit).
+// predecessor's exit as its start.  In the first round a lane whose start
+// changed simply walks its subsequence again from the new start (the raw
+// path typically takes a dozen codewords to meet the true one, and a full
+// walk with two lookups per window costs less than stepping both paths one
+// codeword at a time that far); in later rounds it walks the new path in
+// lockstep with the old one until they meet (the exit stays, the count is
+// re-derived) or the new path leaves the subsequence (a new exit).
 // Rounds end when a wavefront ballot finds no exit changed; after round r
 // lanes 0..r agree with the entry, so at most 64 rounds run, and no budget
 // ever decides the result.
@@ -945,7 +949,10 @@ __device__ void sync_tile(const uint32_t *TTl, int lane, bool act, uint32_t E, u
         bool changed = false;
         if (act && in != start) {
             uint32_t ex, cn;
-            walk_merge<PAIR>(TTl, in, start, exit, cnt, E, st, g, sh, ex, cn);
+            if (round == 0)
+                run_path<PAIR>(TTl, in, E, st, g, sh, ex, cn);
+            else
+                walk_merge<PAIR>(TTl, in, start, exit, cnt, E, st, g, sh, ex, cn);
             changed = ex != exit;
             start = in;
             exit = ex;
@@ -981,8 +988,17 @@ __device__ uint32_t sync_and_store(const SyncArgs &a, uint64_t t, uint32_t *TTl,
     const uint32_t total = static_cast<uint32_t>(wave_sum_u64(cnt));
     const uint32_t last_exit = __shfl(exit, 63, 64);
     if (with_record) {
-        // entry independence of lane 0: walk its subsequence from every entry
-        const uint32_t *TT0 = TTl - lane;
+        // entry independence of lane 0: walk its subsequence from every entry.
+        // Every lane first copies lane 0's units into its own column (reads
+        // of one address are broadcast), so the probe walks conflict-free.
+        wave_lds_sync();
+        {
+            const uint32_t *c0 = TTl - lane;
+            for (uint32_t w = 1; w <= (S >> 5) + 1; ++w)
+                TTl[w * 64] = c0[w * 64];
+        }
+        wave_lds_sync();
+        const uint32_t *TT0 = TTl;
         const uint32_t st0 = __shfl(start, 0, 64), ex0 = __shfl(exit, 0, 64);
         const uint32_t cn0 = __shfl(cnt, 0, 64), E0 = __shfl(E, 0, 64);
         uint32_t exg = ex0, cng = cn0;
@@ -1310,7 +1326,7 @@ uint32_t auto_stage_for(const hd_stream_info &si)
 // workgroup LDS footprint of table + wpg * area (ties: the smaller
 // workgroup).  The table is shared by a workgroup's wavefronts, so larger
 // workgroups amortize it; the LDS of a CU is what bounds residency.
-uint32_t occupancy_wpg(uint32_t table, uint32_t area, const DeviceInfo *dev)
+uint32_t occupancy_wpg(uint32_t table, uint32_t area, const DeviceInfo *dev, uint32_t *waves = nullptr)
 {
     uint32_t best = 0, best_waves = 0;
     for (uint32_t w = 1; w <= kMaxWavesPerGroup; ++w) {
@@ -1323,7 +1339,22 @@ uint32_t occupancy_wpg(uint32_t table, uint32_t area, const DeviceInfo *dev)
             best_waves = fit * w;
         }
     }
+    if (waves)
+        *waves = best_waves;
     return best;
+}
+
+// Largest staging size (a multiple of 64) whose layout still keeps `target`
+// wavefronts resident per CU; 256 when none does.
+uint32_t stage_for_waves(uint32_t table, uint32_t S, uint32_t target, const DeviceInfo *dev)
+{
+    for (uint32_t st = 16384; st > 256; st -= 64) {
+        uint32_t waves = 0;
+        occupancy_wpg(table, wave_area_bytes(S, st), dev, &waves);
+        if (waves >= target)
+            return st;
+    }
+    return 256;
 }
 
 hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
@@ -1761,23 +1792,55 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
     // table, subsequence and staging of the batch; waves per workgroup and
     // workgroups per CU come from per_stream[0] (zero: the most resident
     // wavefronts that layout allows)
-    uint32_t S_alloc = 32, stage_alloc = 256, k1_alloc = 1, n_pair = 0;
+    uint32_t S_alloc = 32, stage_alloc = 256, k1_alloc = 1, n_pair = 0, auto_max = 0;
     std::vector<uint32_t> stage(n_streams);
+    std::vector<bool> given(n_streams);
     for (uint32_t i = 0; i < n_streams; ++i) {
         const hd_stream_info &si = streams[i].info;
         const hd_tune *tu = per_stream ? &per_stream[i] : nullptr;
-        stage[i] = tu && tu->stage_symbols ? tu->stage_symbols : auto_stage_for(si);
+        given[i] = tu && tu->stage_symbols;
+        stage[i] = given[i] ? tu->stage_symbols : auto_stage_for(si);
         if (stage[i] < 256 || stage[i] > 16384 || stage[i] % 64)
             return HD_ERR_ARG;
+        if (!given[i])
+            auto_max = std::max(auto_max, stage[i]);
         if ((si.n_symbols && !outs[i]) || reinterpret_cast<uintptr_t>(outs[i]) % 16 ||
             reinterpret_cast<uintptr_t>(streams[i].words) % 16)
             return HD_ERR_ARG;
         if (64 % si.chunk_subseqs)
             return HD_ERR_UNSUPPORTED;
         S_alloc = std::max(S_alloc, si.subseq_bits);
-        stage_alloc = std::max(stage_alloc, stage[i]);
+        if (given[i])
+            stage_alloc = std::max(stage_alloc, stage[i]);
         k1_alloc = std::max(k1_alloc, streams[i].table->k1);
         n_pair += streams[i].table->pair ? 1u : 0u;
+    }
+    if (auto_max) {
+        // default staging: the largest need of the batch, capped where it
+        // would cost occupancy for everyone -- at the larger of the size that
+        // keeps 16 wavefronts resident per CU and the symbol-weighted median
+        // need (streams above the cap decode their larger tiles in passes)
+        std::vector<std::pair<uint32_t, uint64_t>> need;
+        uint64_t total = 0;
+        for (uint32_t i = 0; i < n_streams; ++i)
+            if (!given[i]) {
+                need.emplace_back(stage[i], streams[i].info.n_symbols);
+                total += streams[i].info.n_symbols;
+            }
+        std::sort(need.begin(), need.end());
+        uint32_t median = need.back().first;
+        uint64_t acc = 0;
+        for (const auto &nd : need)
+            if ((acc += nd.second) * 2 >= total) {
+                median = nd.first;
+                break;
+            }
+        const uint32_t cap = std::max(median, stage_for_waves(table_lds_bytes(k1_alloc), S_alloc, 16, dev));
+        const uint32_t use = std::min(auto_max, cap);
+        for (uint32_t i = 0; i < n_streams; ++i)
+            if (!given[i])
+                stage[i] = std::min(stage[i], use);
+        stage_alloc = std::max(stage_alloc, use);
     }
     const uint32_t table = table_lds_bytes(k1_alloc), area = wave_area_bytes(S_alloc, stage_alloc);
     const hd_tune *t0 = per_stream ? &per_stream[0] : nullptr;

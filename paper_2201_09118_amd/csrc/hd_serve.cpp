@@ -270,7 +270,7 @@ void hd_server::loop()
             cv.wait_for(lk, std::chrono::milliseconds(5));
         else {
             lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            std::this_thread::sleep_for(std::chrono::microseconds(5));
             lk.lock();
         }
     }

@@ -90,13 +90,17 @@ def _percentiles(lat):
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
-def run_served(server: hd.Server, pool, times, which, check=None):
-    """Feeds the schedule to the server.  check(i, ptr, n) may inspect each output."""
+def run_served(server: hd.Server, pool, times, which, check=None, check_every: int = 1, defer: bool = True):
+    """Feeds the schedule to the server.  check(i, ptr, n) inspects the output
+    of every check_every-th request: with defer, after the timed run (those
+    outputs are held until then, so checking never delays the schedule; the
+    budget must leave room for them), else as each completes."""
     n_req = len(times)
     start = time.perf_counter() + 0.01
     sched = start + np.asarray(times)
     lat = np.zeros(n_req)
     rid_to_i = {}
+    held = []
     nxt = 0
     done = 0
     symbols = 0
@@ -113,15 +117,26 @@ def run_served(server: hd.Server, pool, times, which, check=None):
             lat[i] = t_done - sched[i]
             n = pool[which[i]].n_symbols
             symbols += n
-            if check is not None:
+            if check is not None and i % check_every == 0:
+                if defer:
+                    held.append((i, rid, ptr, n))
+                    done += 1
+                    continue
                 check(i, ptr, n)
             server.release(rid)
             done += 1
-        if nxt < n_req and done < n_req:
+        if nxt < n_req:
+            # sleep only while the next arrival is far off, then spin, so that
+            # requests are submitted on time (as the serial server's loop does)
             wait = sched[nxt] - time.perf_counter()
-            if wait > 2e-4:
-                time.sleep(min(wait, 1e-3) / 2)
+            if wait > 2e-3:
+                time.sleep(wait - 1e-3)
+        elif done < n_req:
+            time.sleep(1e-4)       # latency is stamped by the server, not by this poll
     wall = time.perf_counter() - start
+    for i, rid, ptr, n in held:
+        check(i, ptr, n)
+        server.release(rid)
     p50, p99 = _percentiles(lat)
     return {"requests": n_req, "symbols": symbols, "wall_s": wall, "gbs": 2.0 * symbols / wall / 1e9,
             "p50_ms": p50 * 1e3, "p99_ms": p99 * 1e3, "latency_s": lat}

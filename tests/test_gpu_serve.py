@@ -71,7 +71,7 @@ def test_tight_budget_queues_but_completes():
         if not np.array_equal(serve.copy_from_device(ptr, n), cases[which[i]].x):
             bad.append(i)
 
-    res = serve.run_served(server, dss, times, which, check)
+    res = serve.run_served(server, dss, times, which, check, defer=False)
     st = server.stats()
     assert not bad
     assert st["done"] == 24 and st["arena_peak"] <= budget
