@@ -77,6 +77,32 @@ def test_even_length_code_odd_entries():
     _check_ss(make_case(x, 4, 2, 64, 32))
 
 
+def test_interleaved_runs_of_entry_dependent_tiles():
+    """Segments of the codewords 00 and 01 only (a path from an odd offset
+    reads 00 or 10 there and never meets the even ones: every such tile is
+    entry-dependent) alternate with segments that use the 3-bit codewords
+    (which resynchronize), so one stream holds many separate runs of
+    dependent tiles, several per 64-tile window."""
+    rng = np.random.default_rng(8)
+    # lengths: symbols 0..2 get 2 bits, 3..4 get 3 bits (Kraft: 3/4 + 2/8 = 1)
+    hist = np.array([1000, 1000, 1000, 1, 1], np.uint64)
+    ln, cd = oracle.build_codebook(np.repeat(np.arange(5, dtype=np.uint16), hist.astype(np.int64)), 5, 3)
+    assert sorted(ln.tolist()) == [2, 2, 2, 3, 3]
+    parts = []
+    for i in range(160):
+        n = int(rng.integers(2_000, 40_000))
+        if i % 2 == 0:
+            parts.append(rng.choice(np.flatnonzero((ln == 2) & (cd < 2)), n).astype(np.uint16))
+        else:
+            parts.append(rng.integers(0, 5, n // 8).astype(np.uint16))
+    x = np.concatenate(parts)
+    case = make_case(x, 5, 3, 64, 32, ln, cd)
+    _, _, sb = oracle.selfsync(case.enc.words, case.enc.n_bits, x.size, ln, cd, 64)
+    assert (sb > 64 * 64).sum() > 1000           # raw paths that stay off for more than a tile
+    flush(f"interleaved dependent runs: {x.size} symbols, {case.enc.gap.size // 64} tiles")
+    _check_ss(case)
+
+
 def test_all_one_bit_codes_selfsync():
     rng = np.random.default_rng(5)
     x = rng.integers(0, 2, 400_000).astype(np.uint16)
