@@ -175,6 +175,26 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {src.numel() * 2} bytes read and written")
         del src, dst
+    # achievable HBM bandwidth on this machine: a 1 GiB device-to-device copy
+    # (read + write bytes over its time), the practical ceiling beside the
+    # datasheet peak (skipped in counter runs, whose only copy is the
+    # calibration copy)
+    copy_gbs = None
+    if not args.calibrate_copy:
+        csrc = torch.empty(1 << 29, dtype=torch.int16, device=dev).fill_(3)
+        cdst = torch.empty_like(csrc)
+        for _ in range(2):
+            cdst.copy_(csrc)
+        torch.cuda.synchronize()
+        ca, cb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ca.record(stream)
+        for _ in range(5):
+            cdst.copy_(csrc)
+        cb.record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = 2.0 * csrc.numel() * 2 * 5 / (ca.elapsed_time(cb) * 1e-3) / 1e9
+        del csrc, cdst
+        log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     tab = hd.Table(ln, cd, L, args.lut_bits)
     tune = hd.Tune(args.wpg, args.stage, args.groups_per_cu, 0)
     out = torch.empty(n, dtype=torch.int16, device=dev)
@@ -276,6 +296,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "kernel": "k_decode_gap",
                      "kernel_ms": round(head["k_ms"], 5), "alg_bytes_per_launch": alg_bytes,
+                     "copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
+                     "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
                      "decoded_output_gbs_kernel": round(2.0 * n / (head["k_ms"] * 1e-3) / 1e9, 2)},
         "cpu_baseline": cpu,
         "verified": all(r["verified"] for r in res.values()),
