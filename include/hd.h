@@ -96,7 +96,7 @@ typedef struct {
     uint32_t stage_symbols;   /* LDS output staging per wavefront, in symbols,
                                  a multiple of 64 in [256, 16384]                 */
     uint32_t groups_per_cu;   /* persistent workgroups per compute unit           */
-    uint32_t reserved;
+    uint32_t reserved;        /* unused; set to 0                                 */
 } hd_tune;
 
 /* A device-resident stream.  All pointers are device memory owned by the

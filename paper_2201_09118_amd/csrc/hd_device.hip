@@ -438,10 +438,12 @@ __device__ __forceinline__ uint32_t slow_group(uint32_t v, const SmemTable &st, 
 // Walks from q (bit position + 31) over every codeword that starts before
 // qe and returns their count; q is left on the first start at or after qe.
 // Two table lookups per window read: after a fast group (<= k1 <= 14 bits)
-// the 32-bit window still holds at least k1 unread bits.  A group is taken
-// while all its codewords surely start before the end (group start + k1 <=
-// qe); the last few codewords go one lookup at a time, and a pair's second
-// codeword that starts at or past the end is given back.
+// the 32-bit window still holds at least k1 unread bits.  Every codeword is
+// counted by its own start: a group's second codeword, or the second group,
+// only while it starts before qe, and q advances over the counted codewords
+// only, so it ends exactly on the first start at or after qe.  (One loop to
+// the end: a separate loop for the last few codewords cost a whole extra
+// iteration for the slowest lane of every wavefront.)
 template <bool PAIR>
 __device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q, uint32_t qe,
                                                const SmemTable &st, const TableView &g, uint32_t sh,
@@ -449,30 +451,47 @@ __device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q,
 {
     const uint32_t k1 = g.k1;
     uint32_t cnt = 0;
-    while (q + k1 <= qe) {
-        const uint32_t v = window_at(TTl, q);
-        uint32_t a1, n1, a2, n2;
-        const bool fast1 = entry_group<PAIR>(st.lut[v >> sh], k1, a1, n1);
-        if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
-            if (!fast1)
-                slow_group(v, st, g, a1, n1, err);
-        }
-        const bool fast2 = entry_group<PAIR>(st.lut[(v << (a1 & 31u)) >> sh], k1, a2, n2);
-        const bool take2 = fast1 && fast2 && q + a1 + k1 <= qe;
-        q += a1 + (take2 ? a2 : 0u);
-        cnt += n1 + (take2 ? n2 : 0u);
-    }
-    uint32_t qm = q, l2 = 0;
     while (q < qe) {
-        uint32_t s1, s2, l1;
-        lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
-        qm = q + l1;
-        q = qm + l2;
-        cnt += 1 + (l2 != 0);
-    }
-    if (PAIR && l2 != 0 && qm >= qe) {
-        --cnt;
-        q = qm;
+        const uint32_t v = window_at(TTl, q);
+        const uint32_t e1 = st.lut[v >> sh];
+        uint32_t l1, l2;
+        bool fast1;
+        if (PAIR) {
+            l1 = (e1 >> 24) & 0xfu;
+            l2 = e1 >> 28;
+            fast1 = e1 >= (1u << 24);
+        } else {
+            l1 = e1 >> 16;
+            l2 = 0;
+            fast1 = l1 - 1u < k1;
+        }
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
+            if (!fast1) {
+                uint32_t a, n;
+                slow_group(v, st, g, a, n, err);
+                l1 = a;
+                l2 = 0;
+            }
+        }
+        const bool two1 = PAIR && l2 != 0 && q + l1 < qe;
+        const uint32_t a1 = l1 + (two1 ? l2 : 0u);
+        const uint32_t q1 = q + a1;
+        uint32_t m1, m2;
+        bool fast2;
+        const uint32_t e2 = st.lut[(v << (a1 & 31u)) >> sh];
+        if (PAIR) {
+            m1 = (e2 >> 24) & 0xfu;
+            m2 = e2 >> 28;
+            fast2 = e2 >= (1u << 24);
+        } else {
+            m1 = e2 >> 16;
+            m2 = 0;
+            fast2 = m1 - 1u < k1;
+        }
+        const bool take2 = fast1 && fast2 && q1 < qe;
+        const bool two2 = PAIR && take2 && m2 != 0 && q1 + m1 < qe;
+        q = q1 + (take2 ? m1 + (two2 ? m2 : 0u) : 0u);
+        cnt += 1u + two1 + take2 + two2;
     }
     return cnt;
 }
@@ -601,8 +620,9 @@ __host__ __device__ __forceinline__ uint32_t wave_area_bytes(uint32_t S, uint32_
 // A lane's inputs for one tile: its subsequence's units and the next unit,
 // its gap byte and its successor's, and the output offsets bounding its
 // chunk.  Loaded into registers (one tile ahead in the single-stream kernel).
-struct TileIn {
-    uint32_t pw[kMaxUnitsPerLane];
+template <uint32_t MAXU>
+struct TileInT {
+    uint32_t pw[MAXU];
     uint32_t pwn = 0, gk = 0, gn = 0;
     uint64_t c_lo = 0, c_hi = 0;
 
@@ -613,7 +633,7 @@ struct TileIn {
         const uint32_t *src = words + k * wps;
         if ((wps & 3) == 0) {
 #pragma unroll
-            for (uint32_t i = 0; i < kMaxUnitsPerLane / 4; ++i)
+            for (uint32_t i = 0; i < MAXU / 4; ++i)
                 if (4 * i < wps) {
                     const uint4 v = *reinterpret_cast<const uint4 *>(src + 4 * i);
                     pw[4 * i] = v.x;
@@ -623,7 +643,7 @@ struct TileIn {
                 }
         } else {
 #pragma unroll
-            for (uint32_t i = 0; i < kMaxUnitsPerLane; ++i)
+            for (uint32_t i = 0; i < MAXU; ++i)
                 if (i < wps)
                     pw[i] = src[i];
         }
@@ -647,13 +667,40 @@ struct TileIn {
     {
         if (act) {
 #pragma unroll
-            for (uint32_t i = 0; i < kMaxUnitsPerLane; ++i)
+            for (uint32_t i = 0; i < MAXU; ++i)
                 if (i < wps)
                     TTl[(i + 1) * 64] = pw[i];
             TTl[(wps + 1) * 64] = pwn;
         }
     }
 };
+using TileIn = TileInT<kMaxUnitsPerLane>;
+
+// Writes staged output [g0, g1) (global indices; the stage starts at the
+// 16-byte group holding g0) with 16-byte stores where a whole group is in
+// range, else symbol by symbol.
+__device__ __forceinline__ void flush_stage(const StreamDev &sd, const uint16_t *stage, int lane, uint64_t g0,
+                                            uint64_t g1, uint32_t &err)
+{
+    if (g1 > sd.n) {
+        err |= kErrOutRange;
+        g1 = sd.n;
+    }
+    if (g0 < g1) {
+        const uint64_t gb0 = g0 & ~uint64_t(7);
+        const uint32_t ngroups = static_cast<uint32_t>((g1 - gb0 + 7) >> 3);
+        for (uint32_t gi = lane; gi < ngroups; gi += 64) {
+            const uint64_t gs = gb0 + 8ull * gi;
+            if (gs >= g0 && gs + 8 <= g1) {
+                *reinterpret_cast<uint4 *>(sd.out + gs) = *reinterpret_cast<const uint4 *>(stage + 8 * gi);
+            } else {
+                for (uint32_t e = 0; e < 8; ++e)
+                    if (gs + e >= g0 && gs + e < g1)
+                        sd.out[gs + e] = stage[8 * gi + e];
+            }
+        }
+    }
+}
 
 // Steps 2-4 for one wavefront tile whose units are already in TT.
 template <bool PAIR>
@@ -757,31 +804,12 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
             q += l1;
         }
         wave_lds_sync();
-        uint64_t g0 = gbase + pb;
-        uint64_t g1 = gbase + min(lim_rel, total);
-        if (g1 > sd.n) {
-            err |= kErrOutRange;
-            g1 = sd.n;
-        }
-        if (g0 < g1) {
-            const uint64_t gb0 = g0 & ~uint64_t(7);
-            const uint32_t ngroups = static_cast<uint32_t>((g1 - gb0 + 7) >> 3);
-            for (uint32_t gi = lane; gi < ngroups; gi += 64) {
-                const uint64_t gs = gb0 + 8ull * gi;
-                if (gs >= g0 && gs + 8 <= g1) {
-                    *reinterpret_cast<uint4 *>(sd.out + gs) = *reinterpret_cast<const uint4 *>(stage + 8 * gi);
-                } else {
-                    for (uint32_t e = 0; e < 8; ++e)
-                        if (gs + e >= g0 && gs + e < g1)
-                            sd.out[gs + e] = stage[8 * gi + e];
-                }
-            }
-        }
+        flush_stage(sd, stage, lane, gbase + pb, gbase + min(lim_rel, total), err);
         wave_lds_sync();
     }
 }
 
-template <bool PAIR>
+template <bool PAIR, uint32_t MAXU>
 __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -806,7 +834,7 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
     const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * wpg;
     // Tile inputs travel through registers one tile ahead: while tile t is
     // decoded, the inputs of the wavefront's next tile are in flight.
-    TileIn in;
+    TileInT<MAXU> in;
     uint64_t t = static_cast<uint64_t>(blockIdx.x) * wpg + wv;
     in.load(sd, t, ntiles, lane);
     for (; t < ntiles; t += tstride) {
@@ -1278,6 +1306,42 @@ struct Plan {
     uint32_t grid;
 };
 
+// Resident wavefronts per CU that a kernel's vector registers allow
+// (512 per SIMD lane, allocated in blocks of 8; at most 8 per SIMD).
+uint32_t reg_waves_per_cu(const void *func)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, uint32_t>> memo;
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto &m : memo)
+        if (m.first == func)
+            return m.second;
+    uint32_t waves = 32;
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, func) == hipSuccess && at.numRegs > 0) {
+        const uint32_t alloc = (static_cast<uint32_t>(at.numRegs) + 7) / 8 * 8;
+        waves = 4 * std::max<uint32_t>(1, std::min<uint32_t>(8, 512 / alloc));
+    }
+    memo.emplace_back(func, waves);
+    return waves;
+}
+
+// Units per lane the tile-input registers are sized for: 4 covers
+// subsequences of up to 128 bits with 12 fewer registers than 16.
+constexpr uint32_t kSmallUnits = 4;
+
+template <bool PAIR>
+const void *gap_kernel_of(uint32_t S)
+{
+    return S <= 32 * kSmallUnits ? reinterpret_cast<const void *>(&k_decode_gap<PAIR, kSmallUnits>)
+                                 : reinterpret_cast<const void *>(&k_decode_gap<PAIR, kMaxUnitsPerLane>);
+}
+
+const void *gap_kernel(bool pair, uint32_t S)
+{
+    return pair ? gap_kernel_of<true>(S) : gap_kernel_of<false>(S);
+}
+
 hd_status check_stream(const hd_dstream *s, hd_mode m)
 {
     if (!s || !s->table)
@@ -1326,14 +1390,15 @@ uint32_t auto_stage_for(const hd_stream_info &si)
 // workgroup LDS footprint of table + wpg * area (ties: the smaller
 // workgroup).  The table is shared by a workgroup's wavefronts, so larger
 // workgroups amortize it; the LDS of a CU is what bounds residency.
-uint32_t occupancy_wpg(uint32_t table, uint32_t area, const DeviceInfo *dev, uint32_t *waves = nullptr)
+uint32_t occupancy_wpg(uint32_t table, uint32_t area, const DeviceInfo *dev, uint32_t *waves = nullptr,
+                       uint32_t cap = kMaxWavesPerCu)
 {
     uint32_t best = 0, best_waves = 0;
     for (uint32_t w = 1; w <= kMaxWavesPerGroup; ++w) {
         const uint64_t lds = table + uint64_t(w) * area;
         if (lds > dev->lds_per_block)
             break;
-        const uint32_t fit = std::min<uint32_t>(static_cast<uint32_t>(dev->lds_per_cu / lds), kMaxWavesPerCu / w);
+        const uint32_t fit = std::min<uint32_t>(static_cast<uint32_t>(dev->lds_per_cu / lds), cap / w);
         if (fit * w > best_waves) {
             best = w;
             best_waves = fit * w;
@@ -1366,8 +1431,10 @@ hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
     if (p->stage < 256 || p->stage > 16384 || p->stage % 64)
         return HD_ERR_ARG;
     const uint32_t S = s->info.subseq_bits;
+    const uint32_t reg_cap = reg_waves_per_cu(gap_kernel(s->table->pair, S));
     const uint32_t table = table_lds_bytes(s->table->k1), area = wave_area_bytes(S, p->stage);
-    p->wpg = tune && tune->waves_per_group ? tune->waves_per_group : occupancy_wpg(table, area, dev);
+    p->wpg = tune && tune->waves_per_group ? tune->waves_per_group
+                                           : occupancy_wpg(table, area, dev, nullptr, reg_cap);
     if (p->wpg == 0)
         return HD_ERR_UNSUPPORTED;                   // not even one wavefront fits
     if (p->wpg > kMaxWavesPerGroup)
@@ -1376,7 +1443,7 @@ hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
     if (p->lds_bytes > dev->lds_per_block)
         return HD_ERR_UNSUPPORTED;
     uint32_t fit = static_cast<uint32_t>(dev->lds_per_cu / p->lds_bytes);
-    fit = std::max<uint32_t>(1, std::min<uint32_t>(fit, kMaxWavesPerCu / p->wpg));
+    fit = std::max<uint32_t>(1, std::min<uint32_t>(fit, reg_cap / p->wpg));
     p->groups_per_cu = tune && tune->groups_per_cu ? std::min(tune->groups_per_cu, fit) : fit;
     const uint64_t ntiles = ceil_div(s->info.n_subseq, 64);
     const uint64_t want = ceil_div(ntiles, p->wpg);
@@ -1468,18 +1535,18 @@ hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, h
                           : launch_sync<kWpg, false>(a, grid, lds, stream);
 }
 
-template <bool PAIR>
+template <bool PAIR, uint32_t MAXU>
 hd_status launch_gap(const GapArgs &a, const Plan &p, hipStream_t stream)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_gap<PAIR>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_gap<PAIR, MAXU>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 static_cast<int>(device_info()->lds_per_block)) != hipSuccess)
             return HD_ERR_DEVICE;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_decode_gap<PAIR>), dim3(p.grid), dim3(p.wpg * 64), p.lds_bytes, stream, a);
+    hipLaunchKernelGGL((k_decode_gap<PAIR, MAXU>), dim3(p.grid), dim3(p.wpg * 64), p.lds_bytes, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
 
@@ -1608,7 +1675,10 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     a.sd.stage = p.stage;
     a.status = w.status;
     a.tab = view_of(s->table);
-    return s->table->pair ? launch_gap<true>(a, p, stream) : launch_gap<false>(a, p, stream);
+    const bool small = i.subseq_bits <= 32 * kSmallUnits;
+    if (s->table->pair)
+        return small ? launch_gap<true, kSmallUnits>(a, p, stream) : launch_gap<true, kMaxUnitsPerLane>(a, p, stream);
+    return small ? launch_gap<false, kSmallUnits>(a, p, stream) : launch_gap<false, kMaxUnitsPerLane>(a, p, stream);
 }
 
 extern "C" hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
