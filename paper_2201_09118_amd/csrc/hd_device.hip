@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -309,8 +311,8 @@ __device__ __forceinline__ void wave_lds_sync()
 
 // 32 stream bits of one lane from the wavefront's transposed copy TT of its
 // units: unit w of lane l sits at TT[w * 64 + l], with w = 0 a don't-care
-// slot, w = 1 .. S/32 the lane's own subsequence and w = S/32 + 1 the first
-// unit of the next subsequence.  For a bit r of the subsequence, q = r + 31
+// row (never stored, see tt_of), w = 1 .. S/32 the lane's own subsequence and
+// w = S/32 + 1 the first unit of the next subsequence.  For a bit r of the subsequence, q = r + 31
 // selects the unit pair (q >> 5, q >> 5 + 1) -- one ds_read2st64, all 64
 // lanes on distinct banks -- and the right shift (-r) mod 32 = (~q) mod 32.
 __device__ __forceinline__ uint32_t window_at(const uint32_t *TTl, uint32_t q)
@@ -609,7 +611,16 @@ struct GapArgs {
 // that absorb untaken second-symbol stores.
 __host__ __device__ __forceinline__ uint32_t wave_units_bytes(uint32_t S)
 {
-    return ((S >> 5) + 2) * 64 * 4;
+    return ((S >> 5) + 1) * 64 * 4;
+}
+
+// The wavefront's TT pointer for lane `lane`: row w of TT at byte
+// 256 * (w - 1) of the wavefront's area.  Row 0 is never stored: the window
+// reads it only at a zero shift, where its value drops out, and it lies on
+// LDS that precedes the area (the table, or the previous wavefront's area).
+__device__ __forceinline__ uint32_t *tt_of(unsigned char *area, int lane)
+{
+    return reinterpret_cast<uint32_t *>(area) - 64 + lane;
 }
 
 __host__ __device__ __forceinline__ uint32_t wave_area_bytes(uint32_t S, uint32_t stage)
@@ -823,7 +834,7 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
     const int wv = threadIdx.x >> 6;
     const uint32_t wps = sd.S >> 5;
     unsigned char *area = smem + table_lds_bytes(g.k1) + wv * wave_area_bytes(sd.S, sd.stage);
-    uint32_t *TTl = reinterpret_cast<uint32_t *>(area) + lane;
+    uint32_t *TTl = tt_of(area, lane);
     uint16_t *stage = reinterpret_cast<uint16_t *>(area + wave_units_bytes(sd.S));
     uint16_t *dummy = stage + sd.stage + lane;
     const uint32_t sh = 32 - g.k1;
@@ -1063,7 +1074,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_sync(SyncArgs a)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const uint32_t wps = a.S >> 5;
-    uint32_t *TTl = reinterpret_cast<uint32_t *>(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S)) + lane;
+    uint32_t *TTl = tt_of(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S), lane);
     const uint32_t sh = 32 - g.k1;
     const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * WPG;
     // (loading the next tile's units one tile ahead measured no faster here)
@@ -1086,7 +1097,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const uint32_t wps = a.S >> 5;
-    uint32_t *TTl = reinterpret_cast<uint32_t *>(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S)) + lane;
+    uint32_t *TTl = tt_of(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S), lane);
     const uint32_t sh = 32 - g.k1;
     for (uint64_t u = static_cast<uint64_t>(blockIdx.x) * WPG + wv + 1; u < a.ntiles;
          u += static_cast<uint64_t>(gridDim.x) * WPG) {
@@ -1167,7 +1178,7 @@ __global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     unsigned char *area = smem + table_lds_bytes(a.k1_alloc) + wv * wave_area_bytes(a.S_alloc, a.stage_alloc);
-    uint32_t *TTl = reinterpret_cast<uint32_t *>(area) + lane;
+    uint32_t *TTl = tt_of(area, lane);
     uint16_t *stage = reinterpret_cast<uint16_t *>(area + wave_units_bytes(a.S_alloc));
     uint16_t *dummy = stage + a.stage_alloc + lane;
     uint32_t err = 0;
@@ -1306,6 +1317,46 @@ struct Plan {
     uint32_t grid;
 };
 
+// Raises a kernel's dynamic-LDS limit to the device's per-workgroup maximum
+// (once per kernel); launches and occupancy queries both need it.
+bool allow_full_lds(const void *func)
+{
+    static std::mutex mu;
+    static std::vector<const void *> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (std::find(done.begin(), done.end(), func) != done.end())
+        return true;
+    const DeviceInfo *dev = device_info();
+    if (!dev || hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(dev->lds_per_block)) != hipSuccess)
+        return false;
+    done.push_back(func);
+    return true;
+}
+
+// Workgroups of `threads` work-items with `lds` bytes of dynamic LDS that
+// the runtime reports resident per CU for a kernel (memoized); -1 when the
+// query fails.
+int resident_groups(const void *func, uint32_t threads, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, uint32_t, size_t>, int> memo;
+    const auto key = std::make_tuple(func, threads, lds);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = memo.find(key);
+        if (it != memo.end())
+            return it->second;
+    }
+    int nb = -1;
+    if (!allow_full_lds(func) ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, func, static_cast<int>(threads), lds) != hipSuccess)
+        nb = -1;
+    std::lock_guard<std::mutex> lk(mu);
+    memo[key] = nb;
+    return nb;
+}
+
 // Resident wavefronts per CU that a kernel's vector registers allow
 // (512 per SIMD lane, allocated in blocks of 8; at most 8 per SIMD).
 uint32_t reg_waves_per_cu(const void *func)
@@ -1389,20 +1440,43 @@ uint32_t auto_stage_for(const hd_stream_info &si)
 // Wavefronts per workgroup with the most resident wavefronts per CU for a
 // workgroup LDS footprint of table + wpg * area (ties: the smaller
 // workgroup).  The table is shared by a workgroup's wavefronts, so larger
-// workgroups amortize it; the LDS of a CU is what bounds residency.
-uint32_t occupancy_wpg(uint32_t table, uint32_t area, const DeviceInfo *dev, uint32_t *waves = nullptr,
-                       uint32_t cap = kMaxWavesPerCu)
+// workgroups amortize it.  The rule is conservative where measurement showed
+// the naive one wrong: workgroups come in multiples of 4 wavefronts (spread
+// evenly over the 4 SIMDs of a CU), at most 7 wavefronts per SIMD (scalar
+// registers), 4 KB of a CU's LDS kept in reserve, and never more
+// workgroups than the runtime reports resident.  Workgroups of 13 or 14
+// wavefronts, or LDS filled to the last kilobytes, measured 30 % slower: the
+// last workgroup of each CU did not become resident with the others.
+constexpr uint32_t kSimdWaveCap = 7;
+constexpr uint32_t kLdsReserve = 4096;
+
+uint64_t lds_cu_usable(const DeviceInfo *dev)
 {
+    return dev->lds_per_cu > kLdsReserve ? dev->lds_per_cu - kLdsReserve : dev->lds_per_cu;
+}
+
+uint32_t occupancy_wpg(uint32_t table, uint32_t area, const DeviceInfo *dev, uint32_t *waves = nullptr,
+                       uint32_t cap = kMaxWavesPerCu, const void *func = nullptr)
+{
+    cap = std::min<uint32_t>(cap, 4 * kSimdWaveCap);
+    const uint64_t lds_cu = lds_cu_usable(dev);
     uint32_t best = 0, best_waves = 0;
-    for (uint32_t w = 1; w <= kMaxWavesPerGroup; ++w) {
+    for (uint32_t w = 4; w <= kMaxWavesPerGroup; w += 4) {
         const uint64_t lds = table + uint64_t(w) * area;
         if (lds > dev->lds_per_block)
             break;
-        const uint32_t fit = std::min<uint32_t>(static_cast<uint32_t>(dev->lds_per_cu / lds), cap / w);
+        uint32_t fit = std::min<uint32_t>(static_cast<uint32_t>(lds_cu / lds), cap / w);
+        const int nb = func ? resident_groups(func, w * 64, lds) : -1;
+        if (nb >= 0)
+            fit = std::min<uint32_t>(fit, static_cast<uint32_t>(nb));
         if (fit * w > best_waves) {
             best = w;
             best_waves = fit * w;
         }
+    }
+    if (best == 0 && table + uint64_t(area) <= dev->lds_per_block) {
+        best = 1;                      // a layout so large that only one wavefront fits
+        best_waves = 1;
     }
     if (waves)
         *waves = best_waves;
@@ -1422,19 +1496,48 @@ uint32_t stage_for_waves(uint32_t table, uint32_t S, uint32_t target, const Devi
     return 256;
 }
 
+// Default staging of a stream: within 1.05 .. 1.25 times the mean tile
+// output (+64), the size that keeps the most wavefronts resident per CU,
+// the larger one among equals (tiles above it are written in passes).
+uint32_t occupancy_stage(const hd_stream_info &si, uint32_t table, uint32_t reg_cap, const DeviceInfo *dev,
+                         const void *func)
+{
+    const double per_tile = si.n_bits ? 64.0 * si.subseq_bits * double(si.n_symbols) / double(si.n_bits) : 1024.0;
+    auto clamp64 = [](double v) {
+        const uint32_t st = (static_cast<uint32_t>(v) + 63) / 64 * 64;
+        return std::min<uint32_t>(8192, std::max<uint32_t>(512, st));
+    };
+    const uint32_t lo = clamp64(per_tile * 1.05 + 64), hi = clamp64(per_tile * 1.25 + 64);
+    uint32_t best = hi, best_waves = 0;
+    for (uint32_t st = hi; st >= lo; st -= 64) {
+        uint32_t waves = 0;
+        occupancy_wpg(table, wave_area_bytes(si.subseq_bits, st), dev, &waves, reg_cap, func);
+        if (waves > best_waves) {
+            best = st;
+            best_waves = waves;
+        }
+        if (st < 64 + 512)
+            break;
+    }
+    return best;
+}
+
 hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
 {
     const DeviceInfo *dev = device_info();
     if (!dev)
         return HD_ERR_DEVICE;
-    p->stage = tune && tune->stage_symbols ? tune->stage_symbols : auto_stage_for(s->info);
+    const uint32_t S = s->info.subseq_bits;
+    const void *func = gap_kernel(s->table->pair, S);
+    const uint32_t reg_cap = reg_waves_per_cu(func);
+    const uint32_t table = table_lds_bytes(s->table->k1);
+    p->stage = tune && tune->stage_symbols ? tune->stage_symbols
+                                           : occupancy_stage(s->info, table, reg_cap, dev, func);
     if (p->stage < 256 || p->stage > 16384 || p->stage % 64)
         return HD_ERR_ARG;
-    const uint32_t S = s->info.subseq_bits;
-    const uint32_t reg_cap = reg_waves_per_cu(gap_kernel(s->table->pair, S));
-    const uint32_t table = table_lds_bytes(s->table->k1), area = wave_area_bytes(S, p->stage);
+    const uint32_t area = wave_area_bytes(S, p->stage);
     p->wpg = tune && tune->waves_per_group ? tune->waves_per_group
-                                           : occupancy_wpg(table, area, dev, nullptr, reg_cap);
+                                           : occupancy_wpg(table, area, dev, nullptr, reg_cap, func);
     if (p->wpg == 0)
         return HD_ERR_UNSUPPORTED;                   // not even one wavefront fits
     if (p->wpg > kMaxWavesPerGroup)
@@ -1442,8 +1545,11 @@ hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
     p->lds_bytes = table + p->wpg * area;
     if (p->lds_bytes > dev->lds_per_block)
         return HD_ERR_UNSUPPORTED;
-    uint32_t fit = static_cast<uint32_t>(dev->lds_per_cu / p->lds_bytes);
-    fit = std::max<uint32_t>(1, std::min<uint32_t>(fit, reg_cap / p->wpg));
+    uint32_t fit = static_cast<uint32_t>(lds_cu_usable(dev) / p->lds_bytes);
+    fit = std::max<uint32_t>(1, std::min<uint32_t>(fit, std::min<uint32_t>(reg_cap, 4 * kSimdWaveCap) / p->wpg));
+    const int nb = resident_groups(func, p->wpg * 64, p->lds_bytes);
+    if (nb > 0)
+        fit = std::min<uint32_t>(fit, static_cast<uint32_t>(nb));
     p->groups_per_cu = tune && tune->groups_per_cu ? std::min(tune->groups_per_cu, fit) : fit;
     const uint64_t ntiles = ceil_div(s->info.n_subseq, 64);
     const uint64_t want = ceil_div(ntiles, p->wpg);
@@ -1515,6 +1621,7 @@ hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, h
     const uint32_t lds = table_lds_bytes(s->table->k1) + kWpg * wave_units_bytes(i.subseq_bits);
     if (lds > dev->lds_per_block)
         return HD_ERR_UNSUPPORTED;
+    // four groups of eight waves per CU measured faster here than three
     const uint32_t fit = std::max<uint32_t>(1, std::min<uint32_t>(static_cast<uint32_t>(dev->lds_per_cu / lds), 32 / kWpg));
     const uint64_t nt = ceil_div(i.n_subseq, 64);
     const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nt, kWpg),
@@ -1538,14 +1645,8 @@ hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, h
 template <bool PAIR, uint32_t MAXU>
 hd_status launch_gap(const GapArgs &a, const Plan &p, hipStream_t stream)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_gap<PAIR, MAXU>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                static_cast<int>(device_info()->lds_per_block)) != hipSuccess)
-            return HD_ERR_DEVICE;
-        attr_set = true;
-    }
+    if (!allow_full_lds(reinterpret_cast<const void *>(&k_decode_gap<PAIR, MAXU>)))
+        return HD_ERR_DEVICE;
     hipLaunchKernelGGL((k_decode_gap<PAIR, MAXU>), dim3(p.grid), dim3(p.wpg * 64), p.lds_bytes, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
@@ -1786,17 +1887,20 @@ StagingBuf *staging_acquire(size_t bytes)
     return b;
 }
 
+const void *batch_kernel(int formats)
+{
+    switch (formats) {
+    case kBatchPairOnly: return reinterpret_cast<const void *>(&k_decode_batch<kBatchPairOnly>);
+    case kBatchWideOnly: return reinterpret_cast<const void *>(&k_decode_batch<kBatchWideOnly>);
+    default: return reinterpret_cast<const void *>(&k_decode_batch<kBatchMixed>);
+    }
+}
+
 template <int FORMATS>
 hd_status launch_batch_as(const BatchArgs &a, uint32_t wpg, uint32_t lds, uint32_t grid, hipStream_t stream)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decode_batch<FORMATS>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                static_cast<int>(device_info()->lds_per_block)) != hipSuccess)
-            return HD_ERR_DEVICE;
-        attr_set = true;
-    }
+    if (!allow_full_lds(reinterpret_cast<const void *>(&k_decode_batch<FORMATS>)))
+        return HD_ERR_DEVICE;
     hipLaunchKernelGGL(k_decode_batch<FORMATS>, dim3(grid), dim3(wpg * 64), lds, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
@@ -1914,7 +2018,11 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
     }
     const uint32_t table = table_lds_bytes(k1_alloc), area = wave_area_bytes(S_alloc, stage_alloc);
     const hd_tune *t0 = per_stream ? &per_stream[0] : nullptr;
-    const uint32_t wpg = t0 && t0->waves_per_group ? t0->waves_per_group : occupancy_wpg(table, area, dev);
+    const int formats = n_pair == n_streams ? kBatchPairOnly : n_pair == 0 ? kBatchWideOnly : kBatchMixed;
+    const void *func = batch_kernel(formats);
+    const uint32_t reg_cap = reg_waves_per_cu(func);
+    const uint32_t wpg = t0 && t0->waves_per_group ? t0->waves_per_group
+                                                   : occupancy_wpg(table, area, dev, nullptr, reg_cap, func);
     if (wpg == 0)
         return HD_ERR_UNSUPPORTED;
     if (wpg > kMaxWavesPerGroup)
@@ -1922,8 +2030,11 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
     const uint32_t lds = table + wpg * area;
     if (lds > dev->lds_per_block)
         return HD_ERR_UNSUPPORTED;
-    uint32_t fit = std::max<uint32_t>(1, std::min<uint32_t>(static_cast<uint32_t>(dev->lds_per_cu / lds),
-                                                            kMaxWavesPerCu / wpg));
+    uint32_t fit = std::max<uint32_t>(1, std::min<uint32_t>(static_cast<uint32_t>(lds_cu_usable(dev) / lds),
+                                                            std::min<uint32_t>(reg_cap, 4 * kSimdWaveCap) / wpg));
+    const int nb = resident_groups(func, wpg * 64, lds);
+    if (nb > 0)
+        fit = std::min<uint32_t>(fit, static_cast<uint32_t>(nb));
     if (t0 && t0->groups_per_cu)
         fit = std::min(fit, t0->groups_per_cu);
 
@@ -2000,7 +2111,6 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
     a.stage_alloc = stage_alloc;
     a.k1_alloc = k1_alloc;
     const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(items, uint64_t(dev->cus) * fit)));
-    const int formats = n_pair == n_streams ? kBatchPairOnly : n_pair == 0 ? kBatchWideOnly : kBatchMixed;
     return launch_batch(a, formats, wpg, lds, grid, stream);
 }
 
