@@ -82,10 +82,14 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 //                        most k1 bits; length kLenLong for a prefix of a
 //                        longer codeword, kLenBad for a prefix of no
 //                        codeword.  Pair format (alphabet <= 4096, k1 <= 12):
-//                        entry = sym1 | sym2 << 12 | len1 << 24 | len2 << 28,
-//                        the first codeword and, when it also fits in the k1
-//                        bits, the one after it (len2 = 0: none); len1 = 0
-//                        sends the lookup to the per-length limits;
+//                        entry = sym1 | (len1 + len2) << 12 | sym2 << 16 |
+//                        len2 << 28, the first codeword and, when it also
+//                        fits in the k1 bits, the one after it (len2 = 0:
+//                        none).  The bits a group covers, whether it holds
+//                        two codewords, and both symbols as two uint16
+//                        halves (entry & 0x0fff0fff) each take one step;
+//                        len1 + len2 = 0 sends the lookup to the per-length
+//                        limits;
 //   lim   uint64[33]     lim[l] = first canonical code of length l + number
 //                        of codes of length l: a window whose l-bit prefix is
 //                        below lim[l] (and whose shorter prefixes are not
@@ -196,11 +200,11 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
                 const uint32_t e = lut[w], l1 = e >> 16;
                 if (l1 == kLenLong || l1 == kLenBad)
                     continue;                            // len1 = 0: per-length limits
-                uint32_t v = (e & 0xfffu) | (l1 << 24);
+                uint32_t v = (e & 0xfffu) | (l1 << 12);
                 if (l1 < k1) {
                     const uint32_t e2 = lut[(w << l1) & (nlut - 1)], l2 = e2 >> 16;
                     if (l2 != kLenLong && l2 != kLenBad && l2 <= k1 - l1)
-                        v |= ((e2 & 0xfffu) << 12) | (l2 << 28);
+                        v = (e & 0xfffu) | ((l1 + l2) << 12) | ((e2 & 0xfffu) << 16) | (l2 << 28);
                 }
                 two[w] = v;
             }
@@ -317,7 +321,7 @@ __device__ __forceinline__ void wave_lds_sync()
 // lanes on distinct banks -- and the right shift (-r) mod 32 = (~q) mod 32.
 __device__ __forceinline__ uint32_t window_at(const uint32_t *TTl, uint32_t q)
 {
-    const uint32_t *p = TTl + ((q >> 5) << 6);
+    const uint32_t *p = TTl + (__builtin_amdgcn_ubfe(q, 5, 27) << 6);
     return __builtin_amdgcn_alignbit(p[0], p[64], ~q);
 }
 
@@ -371,7 +375,7 @@ __device__ __forceinline__ void load_table(const SmemTable &t, const TableView &
 // codeword longer than the first level (or a window matching no codeword)
 // goes through the per-length limits; an invalid window reports kErrBadCode
 // and consumes one bit so every loop still ends.  In the pair format a valid
-// entry has len1 >= 1, so `entry < 2^24` alone flags the slow case.
+// entry has len1 >= 1, so a zero group length alone flags the slow case.
 template <bool PAIR>
 __device__ __forceinline__ void lookup(const uint32_t *TTl, uint32_t q, const SmemTable &st,
                                        const TableView &g, uint32_t sh, uint32_t &s1,
@@ -382,10 +386,10 @@ __device__ __forceinline__ void lookup(const uint32_t *TTl, uint32_t q, const Sm
     bool slow;
     if (PAIR) {
         s1 = e & 0xfffu;
-        s2 = (e >> 12) & 0xfffu;
-        l1 = (e >> 24) & 0xfu;
+        s2 = (e >> 16) & 0xfffu;
         l2 = e >> 28;
-        slow = e < (1u << 24);
+        l1 = ((e >> 12) & 0xfu) - l2;
+        slow = l1 + l2 == 0;
     } else {
         s1 = e & 0xffffu;
         s2 = 0;
@@ -412,10 +416,9 @@ template <bool PAIR>
 __device__ __forceinline__ bool entry_group(uint32_t e, uint32_t k1, uint32_t &a, uint32_t &n)
 {
     if (PAIR) {
-        const uint32_t l1 = (e >> 24) & 0xfu, l2 = e >> 28;
-        a = l1 + l2;
-        n = 1 + (l2 != 0);
-        return e >= (1u << 24);
+        a = (e >> 12) & 0xfu;
+        n = 1 + (e >= (1u << 28));
+        return a != 0;
     }
     a = e >> 16;
     n = 1;
@@ -440,12 +443,12 @@ __device__ __forceinline__ uint32_t slow_group(uint32_t v, const SmemTable &st, 
 // Walks from q (bit position + 31) over every codeword that starts before
 // qe and returns their count; q is left on the first start at or after qe.
 // Two table lookups per window read: after a fast group (<= k1 <= 14 bits)
-// the 32-bit window still holds at least k1 unread bits.  Every codeword is
-// counted by its own start: a group's second codeword, or the second group,
-// only while it starts before qe, and q advances over the counted codewords
-// only, so it ends exactly on the first start at or after qe.  (One loop to
-// the end: a separate loop for the last few codewords cost a whole extra
-// iteration for the slowest lane of every wavefront.)
+// the 32-bit window still holds at least k1 unread bits.  The loop takes
+// whole groups without looking at qe (one or two codewords each, two groups
+// per iteration); only the last iteration can run past qe, by at most three
+// codewords (a group's second codeword, the second group, its second
+// codeword), and one correction after the loop drops those that start at or
+// after qe and moves q back to the first of them.
 template <bool PAIR>
 __device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q, uint32_t qe,
                                                const SmemTable &st, const TableView &g, uint32_t sh,
@@ -453,47 +456,58 @@ __device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q,
 {
     const uint32_t k1 = g.k1;
     uint32_t cnt = 0;
+    // a1, a2: bits of the last iteration's two groups (a2 = 0: second not
+    // taken); l2, m2: their second codewords' lengths (0: none); m1: the
+    // second group's first length
+    uint32_t a1 = 0, l2 = 0, a2 = 0, m1 = 0, m2 = 0;
     while (q < qe) {
         const uint32_t v = window_at(TTl, q);
         const uint32_t e1 = st.lut[v >> sh];
-        uint32_t l1, l2;
         bool fast1;
         if (PAIR) {
-            l1 = (e1 >> 24) & 0xfu;
+            a1 = (e1 >> 12) & 0xfu;
             l2 = e1 >> 28;
-            fast1 = e1 >= (1u << 24);
+            fast1 = a1 != 0;
         } else {
-            l1 = e1 >> 16;
+            a1 = e1 >> 16;
             l2 = 0;
-            fast1 = l1 - 1u < k1;
+            fast1 = a1 - 1u < k1;
         }
         if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
             if (!fast1) {
                 uint32_t a, n;
                 slow_group(v, st, g, a, n, err);
-                l1 = a;
+                a1 = a;
                 l2 = 0;
             }
         }
-        const bool two1 = PAIR && l2 != 0 && q + l1 < qe;
-        const uint32_t a1 = l1 + (two1 ? l2 : 0u);
-        const uint32_t q1 = q + a1;
-        uint32_t m1, m2;
-        bool fast2;
         const uint32_t e2 = st.lut[(v << (a1 & 31u)) >> sh];
+        bool fast2;
+        uint32_t b2;
         if (PAIR) {
-            m1 = (e2 >> 24) & 0xfu;
+            b2 = (e2 >> 12) & 0xfu;
             m2 = e2 >> 28;
-            fast2 = e2 >= (1u << 24);
+            fast2 = b2 != 0;
         } else {
-            m1 = e2 >> 16;
+            b2 = e2 >> 16;
             m2 = 0;
-            fast2 = m1 - 1u < k1;
+            fast2 = b2 - 1u < k1;
         }
-        const bool take2 = fast1 && fast2 && q1 < qe;
-        const bool two2 = PAIR && take2 && m2 != 0 && q1 + m1 < qe;
-        q = q1 + (take2 ? m1 + (two2 ? m2 : 0u) : 0u);
-        cnt += 1u + two1 + take2 + two2;
+        const bool take2 = fast1 && fast2;
+        a2 = take2 ? b2 : 0u;
+        m1 = b2 - m2;
+        q += a1 + a2;
+        cnt += (PAIR ? 1u + (l2 != 0) : 1u) + (take2 ? (PAIR ? 1u + (m2 != 0) : 1u) : 0u);
+    }
+    if (cnt != 0) {
+        // starts of the last iteration's codewords after its first one
+        const uint32_t q0 = q - a1 - a2;
+        const uint32_t s1 = q0 + a1 - l2, s2 = q0 + a1, s3 = s2 + m1;
+        const bool o1 = PAIR && l2 != 0 && s1 >= qe;
+        const bool o2 = a2 != 0 && s2 >= qe;
+        const bool o3 = PAIR && a2 != 0 && m2 != 0 && s3 >= qe;
+        cnt -= static_cast<uint32_t>(o1) + static_cast<uint32_t>(o2) + static_cast<uint32_t>(o3);
+        q = o1 ? s1 : o2 ? s2 : o3 ? s3 : q;
     }
     return cnt;
 }
@@ -776,28 +790,44 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
         // dst index of symbol j: a0 + excl + j - pb (>= a0 whenever j < jmax)
         uint16_t *dst = stage + (static_cast<int32_t>(a0 + excl) - static_cast<int32_t>(pb));
         // two lookups per window read while at least two full groups remain
-        // in this pass; untaken slots are rewritten by later symbols of the lane
-        while (j + (PAIR ? 4u : 2u) <= jmax) {
-            const uint32_t v = window_at(TTl, q);
-            const uint32_t e1 = st.lut[v >> sh];
-            uint32_t a1, n1, a2, n2;
-            const bool fast1 = entry_group<PAIR>(e1, k1, a1, n1);
-            uint32_t s1 = PAIR ? (e1 & 0xfffu) : (e1 & 0xffffu);
-            if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
-                if (!fast1)
-                    s1 = slow_group(v, st, g, a1, n1, err);
-            }
-            dst[j] = static_cast<uint16_t>(s1);
-            if (PAIR)
-                dst[j + 1] = static_cast<uint16_t>((e1 >> 12) & 0xfffu);
-            j += n1;
-            const uint32_t e2 = st.lut[(v << (a1 & 31u)) >> sh];
-            const bool take2 = entry_group<PAIR>(e2, k1, a2, n2) && fast1;
-            dst[j] = static_cast<uint16_t>(PAIR ? (e2 & 0xfffu) : (e2 & 0xffffu));
-            if (PAIR)
-                dst[j + 1] = static_cast<uint16_t>((e2 >> 12) & 0xfffu);
-            j += take2 ? n2 : 0u;
-            q += a1 + (take2 ? a2 : 0u);
+        // in this pass; untaken slots are rewritten by later symbols of the
+        // lane.  The loop walks the LDS pointer itself.  A group's two symbols
+        // go out as two 16-bit stores: the compiler would merge them into one
+        // 32-bit store at a 2-byte-aligned LDS address, which measured far
+        // slower (the scheduling barrier keeps them apart).
+        constexpr uint32_t kFastMin = PAIR ? 4u : 2u;
+        if (j + kFastMin <= jmax) {
+            uint16_t *pd = dst + j;
+            const uint16_t *const pend = dst + (jmax - kFastMin);
+            do {
+                const uint32_t v = window_at(TTl, q);
+                const uint32_t e1 = st.lut[v >> sh];
+                uint32_t a1, n1, a2, n2;
+                const bool fast1 = entry_group<PAIR>(e1, k1, a1, n1);
+                uint32_t w1 = PAIR ? (e1 & 0x0fff0fffu) : (e1 & 0xffffu);
+                if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
+                    if (!fast1)
+                        w1 = slow_group(v, st, g, a1, n1, err);
+                }
+                pd[0] = static_cast<uint16_t>(w1);
+                __builtin_amdgcn_sched_barrier(0);
+                if (PAIR)
+                    pd[1] = static_cast<uint16_t>(w1 >> 16);
+                pd += n1;
+                const uint32_t e2 = st.lut[(v << (a1 & 31u)) >> sh];
+                const bool take2 = entry_group<PAIR>(e2, k1, a2, n2) && fast1;
+                if (PAIR) {
+                    const uint32_t w2 = e2 & 0x0fff0fffu;
+                    pd[0] = static_cast<uint16_t>(w2);
+                    __builtin_amdgcn_sched_barrier(0);
+                    pd[1] = static_cast<uint16_t>(w2 >> 16);
+                } else {
+                    *pd = static_cast<uint16_t>(e2 & 0xffffu);
+                }
+                pd += take2 ? n2 : 0u;
+                q += a1 + (take2 ? a2 : 0u);
+            } while (pd <= pend);
+            j = static_cast<uint32_t>(pd - dst);
         }
         while (j < jmax) {
             uint32_t s1, s2, l1, l2;
