@@ -284,15 +284,32 @@ namespace {
 
 constexpr int kWave = 64;
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
+// Inclusive prefix sum over the 64 lanes of a wavefront, in registers (DPP):
+// a Kogge-Stone scan inside each row of 16 lanes (shifts 1, 2, 4, 8; a lane
+// whose source lies before its row adds 0), then the row totals -- lane 15's
+// into row 1 and lane 47's into row 3, then lane 31's into rows 2 and 3.
+// Every lane of the wavefront must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int)
 {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t o = __shfl_up(v, d, kWave);
-        if (lane >= d)
-            v += o;
-    }
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xa, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xc, 0xf, false));
     return v;
+}
+
+// Lane l's value, the same in every lane.
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int l)
+{
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), l));
+}
+
+__device__ __forceinline__ uint64_t lane_value64(uint64_t v, int l)
+{
+    return uint64_t(lane_value(static_cast<uint32_t>(v), l)) |
+           (uint64_t(lane_value(static_cast<uint32_t>(v >> 32), l)) << 32);
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
@@ -611,8 +628,18 @@ struct StreamDev {
     const uint64_t *chunk_off;   // [M + 1] output index of each chunk
     uint16_t *out;
     uint64_t n, B, K, M, n_words;
-    uint32_t S, C, stage;        // stage: staging symbols per wave (multiple of 64)
+    uint32_t S, stage;           // stage: staging symbols per wave (multiple of 64)
+    uint32_t Cl;                 // log2 of the chunk size C (C divides 64)
 };
+
+// log2 of a chunk size that divides 64 (checked before any launch)
+inline uint32_t chunk_log2(uint32_t C)
+{
+    uint32_t l = 0;
+    while ((2u << l) <= C)
+        ++l;
+    return l;
+}
 
 struct GapArgs {
     StreamDev sd;
@@ -683,8 +710,8 @@ struct TileInT {
             load_words(sd.words, k, wps);
             gk = sd.gap[k];
             gn = k + 1 < sd.K ? sd.gap[k + 1] : 0u;
-            c_lo = sd.chunk_off[k / sd.C];             // bounds of this lane's chunk
-            c_hi = sd.chunk_off[k / sd.C + 1];         // (k / C + 1 <= M for k < K)
+            c_lo = sd.chunk_off[k >> sd.Cl];           // bounds of this lane's chunk
+            c_hi = sd.chunk_off[(k >> sd.Cl) + 1];     // (k / C + 1 <= M for k < K)
         }
     }
 
@@ -769,12 +796,12 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
     //    the output offset of its first chunk (lane 0's chunk)
     const uint32_t incl = wave_incl_scan(cnt, lane);
     const uint32_t excl = incl - cnt;
-    const uint32_t total = __shfl(incl, 63, 64);
-    const uint64_t gbase = __shfl(c_lo, 0, 64);
+    const uint32_t total = lane_value(incl, 63);
+    const uint64_t gbase = lane_value64(c_lo, 0);
     {
-        const uint32_t cl = lane % sd.C;
+        const uint32_t cl = lane & ((1u << sd.Cl) - 1u);
         const uint32_t excl_first = __shfl(excl, lane - cl, 64);
-        if (act && (cl == sd.C - 1 || k == sd.K - 1)) {
+        if (act && (cl == (1u << sd.Cl) - 1u || k == sd.K - 1)) {
             if (gbase + excl_first != c_lo || gbase + incl != c_hi)
                 err |= kErrChunkSum;
         }
@@ -1802,7 +1829,7 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     a.sd.M = M;
     a.sd.n_words = i.n_words;
     a.sd.S = i.subseq_bits;
-    a.sd.C = ss ? 64u : i.chunk_subseqs;
+    a.sd.Cl = ss ? 6u : chunk_log2(i.chunk_subseqs);
     a.sd.stage = p.stage;
     a.status = w.status;
     a.tab = view_of(s->table);
@@ -2087,7 +2114,7 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
         b.sd.M = si.n_chunks;
         b.sd.n_words = si.n_words;
         b.sd.S = si.subseq_bits;
-        b.sd.C = si.chunk_subseqs;
+        b.sd.Cl = chunk_log2(si.chunk_subseqs);
         b.sd.stage = stage[i];
         b.tab = view_of(s.table);
         b.pair = s.table->pair ? 1 : 0;
