@@ -729,8 +729,10 @@ struct TileInT {
 using TileIn = TileInT<kMaxUnitsPerLane>;
 
 // Writes staged output [g0, g1) (global indices; the stage starts at the
-// 16-byte group holding g0) with 16-byte stores where a whole group is in
-// range, else symbol by symbol.
+// 16-byte group holding g0): whole 16-byte groups with one 16-byte store per
+// lane, then the partial groups at both ends (at most 7 symbols each) with one
+// 2-byte store per lane on lanes 0-15, so no lane walks a group symbol by
+// symbol.  Offsets are relative to that first group (32-bit).
 __device__ __forceinline__ void flush_stage(const StreamDev &sd, const uint16_t *stage, int lane, uint64_t g0,
                                             uint64_t g1, uint32_t &err)
 {
@@ -740,17 +742,18 @@ __device__ __forceinline__ void flush_stage(const StreamDev &sd, const uint16_t 
     }
     if (g0 < g1) {
         const uint64_t gb0 = g0 & ~uint64_t(7);
-        const uint32_t ngroups = static_cast<uint32_t>((g1 - gb0 + 7) >> 3);
-        for (uint32_t gi = lane; gi < ngroups; gi += 64) {
-            const uint64_t gs = gb0 + 8ull * gi;
-            if (gs >= g0 && gs + 8 <= g1) {
-                *reinterpret_cast<uint4 *>(sd.out + gs) = *reinterpret_cast<const uint4 *>(stage + 8 * gi);
-            } else {
-                for (uint32_t e = 0; e < 8; ++e)
-                    if (gs + e >= g0 && gs + e < g1)
-                        sd.out[gs + e] = stage[8 * gi + e];
-            }
-        }
+        uint16_t *const out = sd.out + gb0;
+        const uint32_t h0 = static_cast<uint32_t>(g0 - gb0);      // first symbol, 0..7
+        const uint32_t e1 = static_cast<uint32_t>(g1 - gb0);      // end
+        const uint32_t f0 = (h0 + 7) & ~7u;                       // first whole group
+        const uint32_t f1 = e1 & ~7u;                             // end of whole groups
+        for (uint32_t o = f0 + 8 * lane; o < f1; o += 8 * 64)
+            *reinterpret_cast<uint4 *>(out + o) = *reinterpret_cast<const uint4 *>(stage + o);
+        // head [h0, min(f0, e1)) on lanes 0-7, tail [max(f1, f0), e1) on lanes 8-15
+        const uint32_t o = lane < 8 ? h0 + lane : max(f1, f0) + (lane - 8);
+        const uint32_t lim = lane < 8 ? min(f0, e1) : e1;
+        if (lane < 16 && o < lim)
+            out[o] = stage[o];
     }
 }
 
