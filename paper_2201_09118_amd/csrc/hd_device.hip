@@ -529,6 +529,106 @@ __device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q,
     return cnt;
 }
 
+// Count walk that also keeps, in registers, the first-level entries of its
+// first CAP iterations (pair format only): lg[2i] is iteration i's first
+// group (a codeword longer than k1 becomes a one-symbol entry with a nonzero
+// group-length field), lg[2i+1] its second group or 0 when that was not
+// taken.  The decode step then replays the entries instead of walking the
+// bits again.  nlog = iterations logged; q_cap, cnt_cap = position and count
+// after them (a lane with q_cap < qe went on past the log).  Same results as
+// count_walk.
+template <int CAP>
+__device__ __forceinline__ uint32_t count_walk_log(const uint32_t *TTl, uint32_t &q, uint32_t qe,
+                                                   const SmemTable &st, const TableView &g, uint32_t sh,
+                                                   uint32_t &err, uint32_t (&lg)[2 * CAP], uint32_t &nlog,
+                                                   uint32_t &q_cap, uint32_t &cnt_cap)
+{
+    uint32_t cnt = 0;
+    uint32_t a1 = 0, l2 = 0, a2 = 0, m1 = 0, m2 = 0;
+    // one iteration: two groups from one window read
+    auto step = [&](uint32_t &r1, uint32_t &r2) {
+        const uint32_t v = window_at(TTl, q);
+        uint32_t e1 = st.lut[v >> sh];
+        a1 = (e1 >> 12) & 0xfu;
+        l2 = e1 >> 28;
+        const bool fast1 = a1 != 0;
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
+            if (!fast1) {
+                uint32_t a, n;
+                e1 = slow_group(v, st, g, a, n, err) | (1u << 12);
+                a1 = a;
+                l2 = 0;
+            }
+        }
+        const uint32_t e2 = st.lut[(v << (a1 & 31u)) >> sh];
+        const uint32_t b2 = (e2 >> 12) & 0xfu;
+        m2 = e2 >> 28;
+        const bool take2 = fast1 && b2 != 0;
+        a2 = take2 ? b2 : 0u;
+        m1 = b2 - m2;
+        q += a1 + a2;
+        cnt += 1u + (l2 != 0) + (take2 ? 1u + (m2 != 0) : 0u);
+        r1 = e1;
+        r2 = take2 ? e2 : 0u;
+    };
+    nlog = 0;
+    // fully unrolled: every log entry is assigned once, outside the per-lane
+    // branch (a lane that has stopped logs zeros), so the log maps to fixed
+    // registers
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) {
+        uint32_t r1 = 0, r2 = 0;
+        if (__builtin_amdgcn_ballot_w64(q < qe) != 0) {
+            if (q < qe) {
+                step(r1, r2);
+                nlog = i + 1;
+            }
+        }
+        lg[2 * i] = r1;
+        lg[2 * i + 1] = r2;
+    }
+    q_cap = q;
+    cnt_cap = cnt;
+    while (q < qe) {
+        uint32_t r1, r2;
+        step(r1, r2);
+    }
+    if (cnt != 0) {
+        const uint32_t q0 = q - a1 - a2;
+        const uint32_t s1 = q0 + a1 - l2, s2 = q0 + a1, s3 = s2 + m1;
+        const bool o1 = l2 != 0 && s1 >= qe;
+        const bool o2 = a2 != 0 && s2 >= qe;
+        const bool o3 = a2 != 0 && m2 != 0 && s3 >= qe;
+        cnt -= static_cast<uint32_t>(o1) + static_cast<uint32_t>(o2) + static_cast<uint32_t>(o3);
+        q = o1 ? s1 : o2 ? s2 : o3 ? s3 : q;
+    }
+    return cnt;
+}
+
+// Writes the symbols of the logged entries to dst[0 .. cnt) (the lane's whole
+// output in this pass).  Steps run in lockstep over the entry index, so the
+// log stays in registers; a store that would fall at or past cnt (the unused
+// half of a one-codeword group, codewords of the last iteration past the
+// subsequence end) goes to the lane's dummy slot.
+template <int CAP>
+__device__ __forceinline__ void replay_log(const uint32_t (&lg)[2 * CAP], uint32_t nlog, uint16_t *dst,
+                                           uint32_t cnt, uint16_t *dummy)
+{
+    uint32_t j = 0;
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) {
+        if (static_cast<uint32_t>(i) < nlog) {
+            const uint32_t e1 = lg[2 * i], e2 = lg[2 * i + 1];
+            dst[j] = static_cast<uint16_t>(e1 & 0xfffu);   // an iteration's first codeword is always the lane's
+            *(j + 1 < cnt ? dst + j + 1 : dummy) = static_cast<uint16_t>((e1 >> 16) & 0xfffu);
+            j += 1u + (e1 >= (1u << 28));
+            *(j < cnt ? dst + j : dummy) = static_cast<uint16_t>(e2 & 0xfffu);
+            *(j + 1 < cnt ? dst + j + 1 : dummy) = static_cast<uint16_t>((e2 >> 16) & 0xfffu);
+            j += (e2 != 0 ? 1u : 0u) + (e2 >= (1u << 28));
+        }
+    }
+}
+
 // ------------------------------------------------------------------------
 // Output-index scan over chunks (Sec. III-B, step 3)
 // ------------------------------------------------------------------------
@@ -620,6 +720,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_finish(const uint32_t *__
 // ------------------------------------------------------------------------
 
 constexpr uint32_t kMaxUnitsPerLane = 16;   // subsequences of at most 512 bits
+// Units per lane the tile-input registers are sized for: 4 covers
+// subsequences of up to 128 bits with 12 fewer registers than 16.
+constexpr uint32_t kSmallUnits = 4;
 
 // One stream as the decode kernels see it.
 struct StreamDev {
@@ -757,13 +860,80 @@ __device__ __forceinline__ void flush_stage(const StreamDev &sd, const uint16_t 
     }
 }
 
-// Steps 2-4 for one wavefront tile whose units are already in TT.
+// Decodes this lane's symbols j .. jmax-1 into dst[j .. jmax), walking from q
+// (the bit position of symbol j, + 31); q and j advance.  Two lookups per
+// window read while at least two full groups remain; untaken slots are
+// rewritten by later symbols of the lane.  The loop walks the LDS pointer
+// itself.  A group's two symbols go out as two 16-bit stores: the compiler
+// would merge them into one 32-bit store at a 2-byte-aligned LDS address,
+// which measured far slower (the scheduling barrier keeps them apart).
 template <bool PAIR>
+__device__ __forceinline__ void walk_symbols(const uint32_t *TTl, uint32_t &q, uint32_t &j, uint32_t jmax,
+                                             uint16_t *dst, uint16_t *dummy, const SmemTable &st,
+                                             const TableView &g, uint32_t sh, uint32_t &err)
+{
+    const uint32_t k1 = g.k1;
+    constexpr uint32_t kFastMin = PAIR ? 4u : 2u;
+    if (j + kFastMin <= jmax) {
+        uint16_t *pd = dst + j;
+        const uint16_t *const pend = dst + (jmax - kFastMin);
+        do {
+            const uint32_t v = window_at(TTl, q);
+            const uint32_t e1 = st.lut[v >> sh];
+            uint32_t a1, n1, a2, n2;
+            const bool fast1 = entry_group<PAIR>(e1, k1, a1, n1);
+            uint32_t w1 = PAIR ? (e1 & 0x0fff0fffu) : (e1 & 0xffffu);
+            if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
+                if (!fast1)
+                    w1 = slow_group(v, st, g, a1, n1, err);
+            }
+            pd[0] = static_cast<uint16_t>(w1);
+            __builtin_amdgcn_sched_barrier(0);
+            if (PAIR)
+                pd[1] = static_cast<uint16_t>(w1 >> 16);
+            pd += n1;
+            const uint32_t e2 = st.lut[(v << (a1 & 31u)) >> sh];
+            const bool take2 = entry_group<PAIR>(e2, k1, a2, n2) && fast1;
+            if (PAIR) {
+                const uint32_t w2 = e2 & 0x0fff0fffu;
+                pd[0] = static_cast<uint16_t>(w2);
+                __builtin_amdgcn_sched_barrier(0);
+                pd[1] = static_cast<uint16_t>(w2 >> 16);
+            } else {
+                *pd = static_cast<uint16_t>(e2 & 0xffffu);
+            }
+            pd += take2 ? n2 : 0u;
+            q += a1 + (take2 ? a2 : 0u);
+        } while (pd <= pend);
+        j = static_cast<uint32_t>(pd - dst);
+    }
+    while (j < jmax) {
+        uint32_t s1, s2, l1, l2;
+        lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
+        dst[j] = static_cast<uint16_t>(s1);
+        ++j;
+        if (PAIR) {
+            // second codeword: stored when it is this lane's and in this
+            // pass, else written to the lane's dummy slot
+            const bool two = l2 != 0 && j < jmax;
+            *(two ? dst + j : dummy) = static_cast<uint16_t>(s2);
+            j += two;
+            l1 += two ? l2 : 0u;
+        }
+        q += l1;
+    }
+}
+
+// Steps 2-4 for one wavefront tile whose units are already in TT.  With
+// CAP > 0 (pair format) the count step logs its table entries and a tile whose
+// output fits one staging pass is decoded by replaying them.
+template <bool PAIR, int CAP>
 __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int lane, uint32_t gk_in,
                                             uint32_t gn, uint64_t c_lo, uint64_t c_hi, const uint32_t *TTl,
                                             uint16_t *stage, uint16_t *dummy, const SmemTable &st,
                                             const TableView &g, uint32_t sh, uint32_t &err)
 {
+    static_assert(CAP == 0 || PAIR, "the entry log holds pair-format entries");
     const uint32_t S = sd.S;
     const uint32_t PB = sd.stage - 8;
     const uint64_t k0 = t << 6;
@@ -785,9 +955,14 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
     if (rs > re)
         rs = re;
     const uint32_t qe = re + 31;
-    const uint32_t k1 = g.k1;
     uint32_t q = rs + 31;
-    const uint32_t cnt = count_walk<PAIR>(TTl, q, qe, st, g, sh, err);
+    uint32_t lg[CAP > 0 ? 2 * CAP : 1];
+    uint32_t nlog = 0, q_cap = 0, cnt_cap = 0;
+    uint32_t cnt;
+    if constexpr (CAP > 0)
+        cnt = count_walk_log<CAP>(TTl, q, qe, st, g, sh, err, lg, nlog, q_cap, cnt_cap);
+    else
+        cnt = count_walk<PAIR>(TTl, q, qe, st, g, sh, err);
     // the walk must stop exactly on the next subsequence's start
     if (act) {
         const uint32_t expect = (k + 1 < sd.K) ? S + gn : re;
@@ -812,6 +987,23 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
 
     // 4. decode into LDS staging, flush with 16-byte stores
     const uint32_t a0 = static_cast<uint32_t>(gbase & 7);
+    if constexpr (CAP > 0) {
+        if (total <= PB) {
+            uint16_t *dst = stage + (a0 + excl);
+            replay_log<CAP>(lg, nlog, dst, cnt, dummy);
+            const bool more = q_cap < qe;               // went on past the log
+            if (__builtin_amdgcn_ballot_w64(more) != 0) {
+                if (more) {
+                    uint32_t q2 = q_cap, j2 = cnt_cap;
+                    walk_symbols<PAIR>(TTl, q2, j2, cnt, dst, dummy, st, g, sh, err);
+                }
+            }
+            wave_lds_sync();
+            flush_stage(sd, stage, lane, gbase, gbase + total, err);
+            wave_lds_sync();
+            return;
+        }
+    }
     q = rs + 31;
     uint32_t j = 0;
     for (uint32_t pb = 0; pb < total; pb += PB) {
@@ -819,66 +1011,15 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
         const uint32_t jmax = lim_rel > excl ? min(cnt, lim_rel - excl) : 0u;
         // dst index of symbol j: a0 + excl + j - pb (>= a0 whenever j < jmax)
         uint16_t *dst = stage + (static_cast<int32_t>(a0 + excl) - static_cast<int32_t>(pb));
-        // two lookups per window read while at least two full groups remain
-        // in this pass; untaken slots are rewritten by later symbols of the
-        // lane.  The loop walks the LDS pointer itself.  A group's two symbols
-        // go out as two 16-bit stores: the compiler would merge them into one
-        // 32-bit store at a 2-byte-aligned LDS address, which measured far
-        // slower (the scheduling barrier keeps them apart).
-        constexpr uint32_t kFastMin = PAIR ? 4u : 2u;
-        if (j + kFastMin <= jmax) {
-            uint16_t *pd = dst + j;
-            const uint16_t *const pend = dst + (jmax - kFastMin);
-            do {
-                const uint32_t v = window_at(TTl, q);
-                const uint32_t e1 = st.lut[v >> sh];
-                uint32_t a1, n1, a2, n2;
-                const bool fast1 = entry_group<PAIR>(e1, k1, a1, n1);
-                uint32_t w1 = PAIR ? (e1 & 0x0fff0fffu) : (e1 & 0xffffu);
-                if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
-                    if (!fast1)
-                        w1 = slow_group(v, st, g, a1, n1, err);
-                }
-                pd[0] = static_cast<uint16_t>(w1);
-                __builtin_amdgcn_sched_barrier(0);
-                if (PAIR)
-                    pd[1] = static_cast<uint16_t>(w1 >> 16);
-                pd += n1;
-                const uint32_t e2 = st.lut[(v << (a1 & 31u)) >> sh];
-                const bool take2 = entry_group<PAIR>(e2, k1, a2, n2) && fast1;
-                if (PAIR) {
-                    const uint32_t w2 = e2 & 0x0fff0fffu;
-                    pd[0] = static_cast<uint16_t>(w2);
-                    __builtin_amdgcn_sched_barrier(0);
-                    pd[1] = static_cast<uint16_t>(w2 >> 16);
-                } else {
-                    *pd = static_cast<uint16_t>(e2 & 0xffffu);
-                }
-                pd += take2 ? n2 : 0u;
-                q += a1 + (take2 ? a2 : 0u);
-            } while (pd <= pend);
-            j = static_cast<uint32_t>(pd - dst);
-        }
-        while (j < jmax) {
-            uint32_t s1, s2, l1, l2;
-            lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
-            dst[j] = static_cast<uint16_t>(s1);
-            ++j;
-            if (PAIR) {
-                // second codeword: stored when it is this lane's and in this
-                // pass, else written to the lane's dummy slot
-                const bool two = l2 != 0 && j < jmax;
-                *(two ? dst + j : dummy) = static_cast<uint16_t>(s2);
-                j += two;
-                l1 += two ? l2 : 0u;
-            }
-            q += l1;
-        }
+        walk_symbols<PAIR>(TTl, q, j, jmax, dst, dummy, st, g, sh, err);
         wave_lds_sync();
         flush_stage(sd, stage, lane, gbase + pb, gbase + min(lim_rel, total), err);
         wave_lds_sync();
     }
 }
+
+// Entries logged per lane by the single-stream decode (pair format, S <= 128).
+constexpr int kLogIters = 12;
 
 template <bool PAIR, uint32_t MAXU>
 __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
@@ -915,7 +1056,8 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
         const uint64_t c_lo = in.c_lo, c_hi = in.c_hi;
         in.load(sd, t + tstride, ntiles, lane);
         wave_lds_sync();
-        decode_tile<PAIR>(sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, g, sh, err);
+        decode_tile<PAIR, (PAIR && MAXU == kSmallUnits) ? kLogIters : 0>(sd, t, lane, gk, gn, c_lo, c_hi, TTl,
+                                                                           stage, dummy, st, g, sh, err);
     }
     if (err)
         atomicOr(a.status, err);
@@ -1276,9 +1418,9 @@ __global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
             const SmemTable st = carve_table(smem, bs.tab.k1);
             const uint32_t sh = 32 - bs.tab.k1;
             if (FORMATS == kBatchPairOnly || (FORMATS == kBatchMixed && bs.pair))
-                decode_tile<true>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, bs.tab, sh, err);
+                decode_tile<true, 0>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, bs.tab, sh, err);
             else
-                decode_tile<false>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, bs.tab, sh, err);
+                decode_tile<false, 0>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, bs.tab, sh, err);
         }
         si = nsi;
     }
@@ -1436,10 +1578,6 @@ uint32_t reg_waves_per_cu(const void *func)
     memo.emplace_back(func, waves);
     return waves;
 }
-
-// Units per lane the tile-input registers are sized for: 4 covers
-// subsequences of up to 128 bits with 12 fewer registers than 16.
-constexpr uint32_t kSmallUnits = 4;
 
 template <bool PAIR>
 const void *gap_kernel_of(uint32_t S)

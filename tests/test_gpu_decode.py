@@ -80,6 +80,37 @@ def test_all_one_bit_codes_multi_pass_staging():
         _check(case, ds, tune={"stage_symbols": stage})
 
 
+def test_entry_log_overflow_and_one_pass_replay():
+    """Regions of about 2-bit codes (some 60 codewords per 128-bit
+    subsequence, more than the count step logs: 12 iterations of up to four
+    codewords) alternate with regions of about 5-bit codes.  Lanes past the
+    log finish by walking; a staging buffer that holds a whole tile keeps the
+    one-pass replay, a small one the multi-pass walk; both modes."""
+    rng = np.random.default_rng(11)
+    parts = [hdsynth.two_sided_geometric(rng, 20_000, 0.3 if i % 2 == 0 else 0.7, 1024) for i in range(40)]
+    x = np.concatenate(parts)
+    case = make_case(x, 1024, 24, 128, 32)
+    assert 1.5 < case.enc.n_bits / x.size < 5.0
+    ds = upload(case)
+    for mode in (0, 1):
+        for stage in (0, 512, 8192):
+            flush(f"entry log: mode={mode} stage={stage}")
+            _check(case, ds, mode=mode, tune={"stage_symbols": stage})
+
+
+def test_entry_log_slow_codes():
+    """Every codeword longer than a 6-bit first level: each logged group is a
+    one-symbol entry built from the per-length limits."""
+    rng = np.random.default_rng(12)
+    x = hdsynth.two_sided_geometric(rng, 300_000, 0.98, 4096)
+    case = make_case(x, 4096, 20, 128, 32)
+    assert case.lengths[case.lengths > 0].min() > 6
+    ds = upload(case, lut_bits=6)
+    for stage in (0, 4096):
+        flush(f"entry log slow codes stage={stage}")
+        _check(case, ds, tune={"stage_symbols": stage})
+
+
 def test_all_codes_at_max_length():
     rng = np.random.default_rng(2)
     x = rng.integers(0, 4096, 200_000).astype(np.uint16)
