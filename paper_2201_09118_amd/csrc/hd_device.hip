@@ -1373,7 +1373,7 @@ __device__ __forceinline__ uint32_t batch_stream_of(const BatchArgs &a, uint64_t
 // Table formats a batch launch must handle: all pair, all one-symbol, or both.
 constexpr int kBatchPairOnly = 0, kBatchWideOnly = 1, kBatchMixed = 2;
 
-template <int FORMATS>
+template <int FORMATS, uint32_t MAXU>
 __global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -1389,7 +1389,7 @@ __global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
     uint64_t item = blockIdx.x;
     uint32_t si = batch_stream_of(a, item, 0);
     uint32_t cur = 0xffffffffu;
-    TileIn in;
+    TileInT<MAXU> in;
     if (item < a.n_items) {
         const BatchStreamDev &b0 = a.streams[si];
         in.load(b0.sd, (item - b0.item0) * wpg + wv, b0.ntiles, lane);
@@ -1418,7 +1418,8 @@ __global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
             const SmemTable st = carve_table(smem, bs.tab.k1);
             const uint32_t sh = 32 - bs.tab.k1;
             if (FORMATS == kBatchPairOnly || (FORMATS == kBatchMixed && bs.pair))
-                decode_tile<true, 0>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, bs.tab, sh, err);
+                decode_tile<true, MAXU == kSmallUnits ? kLogIters : 0>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl,
+                                                                       stage, dummy, st, bs.tab, sh, err);
             else
                 decode_tile<false, 0>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, bs.tab, sh, err);
         }
@@ -2085,32 +2086,49 @@ StagingBuf *staging_acquire(size_t bytes)
     return b;
 }
 
-const void *batch_kernel(int formats)
+// The batch kernel for a set of table formats; `small`: every subsequence
+// of the batch has at most 32 * kSmallUnits bits (smaller tile-input
+// registers, and the entry-log replay for pair-format streams).
+template <uint32_t MAXU>
+const void *batch_kernel_of(int formats)
 {
     switch (formats) {
-    case kBatchPairOnly: return reinterpret_cast<const void *>(&k_decode_batch<kBatchPairOnly>);
-    case kBatchWideOnly: return reinterpret_cast<const void *>(&k_decode_batch<kBatchWideOnly>);
-    default: return reinterpret_cast<const void *>(&k_decode_batch<kBatchMixed>);
+    case kBatchPairOnly: return reinterpret_cast<const void *>(&k_decode_batch<kBatchPairOnly, MAXU>);
+    case kBatchWideOnly: return reinterpret_cast<const void *>(&k_decode_batch<kBatchWideOnly, MAXU>);
+    default: return reinterpret_cast<const void *>(&k_decode_batch<kBatchMixed, MAXU>);
     }
 }
 
-template <int FORMATS>
+const void *batch_kernel(int formats, bool small)
+{
+    return small ? batch_kernel_of<kSmallUnits>(formats) : batch_kernel_of<kMaxUnitsPerLane>(formats);
+}
+
+template <int FORMATS, uint32_t MAXU>
 hd_status launch_batch_as(const BatchArgs &a, uint32_t wpg, uint32_t lds, uint32_t grid, hipStream_t stream)
 {
-    if (!allow_full_lds(reinterpret_cast<const void *>(&k_decode_batch<FORMATS>)))
+    if (!allow_full_lds(reinterpret_cast<const void *>(&k_decode_batch<FORMATS, MAXU>)))
         return HD_ERR_DEVICE;
-    hipLaunchKernelGGL(k_decode_batch<FORMATS>, dim3(grid), dim3(wpg * 64), lds, stream, a);
+    hipLaunchKernelGGL((k_decode_batch<FORMATS, MAXU>), dim3(grid), dim3(wpg * 64), lds, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
 
-hd_status launch_batch(const BatchArgs &a, int formats, uint32_t wpg, uint32_t lds, uint32_t grid,
-                       hipStream_t stream)
+template <uint32_t MAXU>
+hd_status launch_batch_of(const BatchArgs &a, int formats, uint32_t wpg, uint32_t lds, uint32_t grid,
+                          hipStream_t stream)
 {
     switch (formats) {
-    case kBatchPairOnly: return launch_batch_as<kBatchPairOnly>(a, wpg, lds, grid, stream);
-    case kBatchWideOnly: return launch_batch_as<kBatchWideOnly>(a, wpg, lds, grid, stream);
-    default: return launch_batch_as<kBatchMixed>(a, wpg, lds, grid, stream);
+    case kBatchPairOnly: return launch_batch_as<kBatchPairOnly, MAXU>(a, wpg, lds, grid, stream);
+    case kBatchWideOnly: return launch_batch_as<kBatchWideOnly, MAXU>(a, wpg, lds, grid, stream);
+    default: return launch_batch_as<kBatchMixed, MAXU>(a, wpg, lds, grid, stream);
     }
+}
+
+hd_status launch_batch(const BatchArgs &a, int formats, bool small, uint32_t wpg, uint32_t lds, uint32_t grid,
+                       hipStream_t stream)
+{
+    return small ? launch_batch_of<kSmallUnits>(a, formats, wpg, lds, grid, stream)
+                 : launch_batch_of<kMaxUnitsPerLane>(a, formats, wpg, lds, grid, stream);
 }
 
 
@@ -2217,7 +2235,8 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
     const uint32_t table = table_lds_bytes(k1_alloc), area = wave_area_bytes(S_alloc, stage_alloc);
     const hd_tune *t0 = per_stream ? &per_stream[0] : nullptr;
     const int formats = n_pair == n_streams ? kBatchPairOnly : n_pair == 0 ? kBatchWideOnly : kBatchMixed;
-    const void *func = batch_kernel(formats);
+    const bool small = S_alloc <= 32 * kSmallUnits;
+    const void *func = batch_kernel(formats, small);
     const uint32_t reg_cap = reg_waves_per_cu(func);
     const uint32_t wpg = t0 && t0->waves_per_group ? t0->waves_per_group
                                                    : occupancy_wpg(table, area, dev, nullptr, reg_cap, func);
@@ -2309,7 +2328,7 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
     a.stage_alloc = stage_alloc;
     a.k1_alloc = k1_alloc;
     const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(items, uint64_t(dev->cus) * fit)));
-    return launch_batch(a, formats, wpg, lds, grid, stream);
+    return launch_batch(a, formats, small, wpg, lds, grid, stream);
 }
 
 extern "C" hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *out, void *workspace,
