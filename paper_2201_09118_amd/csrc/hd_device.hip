@@ -81,7 +81,9 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 //                        entry = symbol | length << 16 for codewords of at
 //                        most k1 bits; length kLenLong for a prefix of a
 //                        longer codeword, kLenBad for a prefix of no
-//                        codeword.  Pair format (alphabet <= 4096, k1 <= 12):
+//                        codeword (for both, the symbol field holds the
+//                        length the per-length search starts at: the
+//                        shortest codeword under that prefix).  Pair format (alphabet <= 4096, k1 <= 12):
 //                        entry = sym1 | (len1 + len2) << 12 | sym2 << 16 |
 //                        len2 << 28, the first codeword and, when it also
 //                        fits in the k1 bits, the one after it (len2 = 0:
@@ -89,7 +91,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 //                        two codewords, and both symbols as two uint16
 //                        halves (entry & 0x0fff0fff) each take one step;
 //                        len1 + len2 = 0 sends the lookup to the per-length
-//                        limits;
+//                        limits, starting at the length in bits 0-5;
 //   lim   uint64[33]     lim[l] = first canonical code of length l + number
 //                        of codes of length l: a window whose l-bit prefix is
 //                        below lim[l] (and whose shorter prefixes are not
@@ -180,11 +182,17 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
                     syms[fill[lengths[s]]++] = static_cast<uint16_t>(s);
         }
         const uint32_t nlut = 1u << k1;
-        std::vector<uint32_t> lut(nlut, kLenBad << 16);
+        std::vector<uint32_t> lut(nlut, (kLenBad << 16) | (k1 + 1));
+        // a prefix of longer codewords: the search over lengths starts at
+        // the shortest codeword under it (every shorter length fails its
+        // limit test for a canonical code)
         for (uint32_t s = 0; s < A; ++s) {
             const uint32_t l = lengths[s];
-            if (l > k1)
-                lut[codes[s] >> (l - k1)] = kLenLong << 16;
+            if (l > k1) {
+                uint32_t &e = lut[codes[s] >> (l - k1)];
+                const uint32_t cur = (e >> 16) == kLenLong ? (e & 0x3fu) : 64u;
+                e = (kLenLong << 16) | std::min(cur, l);
+            }
         }
         for (uint32_t s = 0; s < A; ++s) {
             const uint32_t l = lengths[s];
@@ -198,8 +206,10 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
             std::vector<uint32_t> two(nlut, 0);
             for (uint32_t w = 0; w < nlut; ++w) {
                 const uint32_t e = lut[w], l1 = e >> 16;
-                if (l1 == kLenLong || l1 == kLenBad)
-                    continue;                            // len1 = 0: per-length limits
+                if (l1 == kLenLong || l1 == kLenBad) {
+                    two[w] = e & 0x3fu;                  // len1 + len2 = 0: per-length limits
+                    continue;
+                }
                 uint32_t v = (e & 0xfffu) | (l1 << 12);
                 if (l1 < k1) {
                     const uint32_t e2 = lut[(w << l1) & (nlut - 1)], l2 = e2 >> 16;
@@ -342,12 +352,13 @@ __device__ __forceinline__ uint32_t window_at(const uint32_t *TTl, uint32_t q)
     return __builtin_amdgcn_alignbit(p[0], p[64], ~q);
 }
 
-// Codewords longer than the first level: canonical per-length limits.
-__device__ __forceinline__ uint32_t decode_long(uint32_t v, uint32_t k1, uint32_t L,
+// Codewords longer than the first level: canonical per-length limits,
+// searched from length l0 (from the slow first-level entry; at least k1 + 1).
+__device__ __forceinline__ uint32_t decode_long(uint32_t v, uint32_t l0, uint32_t k1, uint32_t L,
                                              const uint64_t *lim, const int64_t *base,
                                              const uint16_t *syms, uint32_t *len_out)
 {
-    for (uint32_t l = k1 + 1; l <= L; ++l) {
+    for (uint32_t l = max(l0, k1 + 1); l <= L; ++l) {
         const uint64_t c = static_cast<uint64_t>(v) >> (32 - l);
         if (c < lim[l]) {
             *len_out = l;
@@ -416,7 +427,7 @@ __device__ __forceinline__ void lookup(const uint32_t *TTl, uint32_t q, const Sm
     }
     if (__builtin_expect(__builtin_amdgcn_ballot_w64(slow) != 0, 0)) {
         if (slow) {
-            s1 = decode_long(v, g.k1, g.L, st.lim, st.base, g.syms, &l1);
+            s1 = decode_long(v, e & 0x3fu, g.k1, g.L, st.lim, st.base, g.syms, &l1);
             l2 = 0;
             if (l1 == 0) {
                 err |= kErrBadCode;
@@ -442,12 +453,13 @@ __device__ __forceinline__ bool entry_group(uint32_t e, uint32_t k1, uint32_t &a
     return a - 1u < k1;
 }
 
-// Slow first group of a window: one codeword through the per-length limits.
-__device__ __forceinline__ uint32_t slow_group(uint32_t v, const SmemTable &st, const TableView &g,
+// Slow first group of a window (first-level entry e): one codeword through
+// the per-length limits.
+__device__ __forceinline__ uint32_t slow_group(uint32_t v, uint32_t e, const SmemTable &st, const TableView &g,
                                                uint32_t &a, uint32_t &n, uint32_t &err)
 {
     uint32_t l;
-    const uint32_t s = decode_long(v, g.k1, g.L, st.lim, st.base, g.syms, &l);
+    const uint32_t s = decode_long(v, e & 0x3fu, g.k1, g.L, st.lim, st.base, g.syms, &l);
     if (l == 0) {
         err |= kErrBadCode;
         l = 1;
@@ -493,7 +505,7 @@ __device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q,
         if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
             if (!fast1) {
                 uint32_t a, n;
-                slow_group(v, st, g, a, n, err);
+                slow_group(v, e1, st, g, a, n, err);
                 a1 = a;
                 l2 = 0;
             }
@@ -555,7 +567,7 @@ __device__ __forceinline__ uint32_t count_walk_log(const uint32_t *TTl, uint32_t
         if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
             if (!fast1) {
                 uint32_t a, n;
-                e1 = slow_group(v, st, g, a, n, err) | (1u << 12);
+                e1 = slow_group(v, e1, st, g, a, n, err) | (1u << 12);
                 a1 = a;
                 l2 = 0;
             }
@@ -885,7 +897,7 @@ __device__ __forceinline__ void walk_symbols(const uint32_t *TTl, uint32_t &q, u
             uint32_t w1 = PAIR ? (e1 & 0x0fff0fffu) : (e1 & 0xffffu);
             if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
                 if (!fast1)
-                    w1 = slow_group(v, st, g, a1, n1, err);
+                    w1 = slow_group(v, e1, st, g, a1, n1, err);
             }
             pd[0] = static_cast<uint16_t>(w1);
             __builtin_amdgcn_sched_barrier(0);
@@ -1111,6 +1123,8 @@ struct SyncArgs {
     uint32_t *tot;            // [ntiles] codewords per tile
     SyncRec *rec;             // [ntiles]
     uint32_t *status;
+    uint32_t *n_pending;      // tiles step 1 left unconverged (zero at launch)
+    uint32_t *pending;        // [ntiles] their indices
     TableView tab;
     uint64_t B, K, ntiles, n_words;
     uint32_t S;
@@ -1173,17 +1187,24 @@ __device__ __forceinline__ void load_units(uint32_t *TTl, const uint32_t *words,
 }
 
 // Step 1 for one tile with lane 0 starting at e0.
+// Rounds of step 1: enough for any tile (after round r lanes 0..r are final).
+constexpr uint32_t kMaxRounds = 65;
+// Rounds the main sync kernel spends on a tile before handing it to the
+// pending-tile kernel.
+constexpr uint32_t kSyncRounds = 2;
+
+// Returns whether the rounds converged within max_rounds.
 template <bool PAIR>
-__device__ void sync_tile(const uint32_t *TTl, int lane, bool act, uint32_t E, uint32_t S, uint32_t e0,
-                          const SmemTable &st, const TableView &g, uint32_t sh, uint32_t &start,
-                          uint32_t &exit, uint32_t &cnt)
+__device__ bool sync_tile(const uint32_t *TTl, int lane, bool act, uint32_t E, uint32_t S, uint32_t e0,
+                          uint32_t max_rounds, const SmemTable &st, const TableView &g, uint32_t sh,
+                          uint32_t &start, uint32_t &exit, uint32_t &cnt)
 {
     start = lane == 0 ? e0 : 0u;
     exit = start;
     cnt = 0;
     if (act)
         run_path<PAIR>(TTl, start, E, st, g, sh, exit, cnt);
-    for (uint32_t round = 0; round <= 64; ++round) {
+    for (uint32_t round = 0; round < max_rounds; ++round) {
         uint32_t in = __shfl_up(exit, 1, 64) - S;
         if (lane == 0)
             in = e0;
@@ -1200,8 +1221,9 @@ __device__ void sync_tile(const uint32_t *TTl, int lane, bool act, uint32_t E, u
             cnt = cn;
         }
         if (__builtin_amdgcn_ballot_w64(changed) == 0)
-            break;
+            return true;
     }
+    return false;
 }
 
 // Per-lane subsequence end: S, or the stream end for the last subsequence.
@@ -1216,14 +1238,19 @@ __device__ __forceinline__ uint32_t lane_end(uint64_t k, uint64_t K, uint64_t B,
 // returns the next tile's entry implied by the tile's last exit.
 template <bool PAIR>
 __device__ uint32_t sync_and_store(const SyncArgs &a, uint64_t t, uint32_t *TTl, int lane, uint32_t e0,
-                                   bool with_record, const SmemTable &st, const TableView &g, uint32_t sh)
+                                   bool with_record, uint32_t max_rounds, const SmemTable &st,
+                                   const TableView &g, uint32_t sh)
 {
     const uint32_t S = a.S;
     const uint64_t k = (t << 6) + lane;
     const bool act = k < a.K;
     const uint32_t E = lane_end(k, a.K, a.B, S);
     uint32_t start, exit, cnt;
-    sync_tile<PAIR>(TTl, lane, act, E, S, e0, st, g, sh, start, exit, cnt);
+    const bool done = sync_tile<PAIR>(TTl, lane, act, E, S, e0, max_rounds, st, g, sh, start, exit, cnt);
+    // only the round-limited pass lists tiles (each at most once, so the
+    // list index stays below ntiles); kMaxRounds always converges
+    if (!done && max_rounds < kMaxRounds && lane == 0)
+        a.pending[atomicAdd(a.n_pending, 1u)] = static_cast<uint32_t>(t);
     if (act)
         a.gap_s[k] = static_cast<uint8_t>(start);
     const uint32_t total = static_cast<uint32_t>(wave_sum_u64(cnt));
@@ -1244,8 +1271,11 @@ __device__ uint32_t sync_and_store(const SyncArgs &a, uint64_t t, uint32_t *TTl,
         const uint32_t cn0 = __shfl(cnt, 0, 64), E0 = __shfl(E, 0, 64);
         uint32_t exg = ex0, cng = cn0;
         const bool probe = lane < static_cast<int>(g.L);
+        // a full walk per entry (two groups per window read): stepping each
+        // entry's path against lane 0's one codeword at a time until they
+        // meet measured slower (sync kernel 260 vs 201 us on 134 M symbols)
         if (probe && static_cast<uint32_t>(lane) != st0)
-            walk_merge<PAIR>(TT0, lane, st0, ex0, cn0, E0, st, g, sh, exg, cng);
+            run_path<PAIR>(TT0, lane, E0, st, g, sh, exg, cng);
         const bool differs = probe && exg != ex0;
         const bool indep = __builtin_amdgcn_ballot_w64(differs) == 0;
         SyncRec *r = a.rec + t;
@@ -1283,9 +1313,86 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_sync(SyncArgs a)
     for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv; t < a.ntiles; t += tstride) {
         load_units(TTl, a.words, (t << 6) + lane, a.K, wps);
         wave_lds_sync();
-        sync_and_store<PAIR>(a, t, TTl, lane, 0u, true, st, g, sh);
+        sync_and_store<PAIR>(a, t, TTl, lane, 0u, true, kSyncRounds, st, g, sh);
         wave_lds_sync();
     }
+}
+
+// Finishes step 1 for the tiles the sync kernel left unconverged after
+// kSyncRounds rounds (listed in a.pending; typically streams that do not
+// self-synchronize, such as long runs of one codeword, where rounds would
+// fix one lane at a time).  One workgroup per tile: its wavefronts walk
+// every lane's subsequence from every entry g < L (exit and count per entry,
+// in LDS), then one thread chains the entries from lane 0's entry 0 through
+// the lanes.  Lane 0's path and the tile record are already final.
+// LDS: table, the tile's units (one copy), exit and count tables.
+template <int WPG, bool PAIR>
+__global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const TableView &g = a.tab;
+    const SmemTable st = carve_table(smem, g.k1);
+    load_table(st, g);
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const uint32_t wps = a.S >> 5;
+    unsigned char *units = smem + table_lds_bytes(g.k1);
+    const uint32_t *TTl = tt_of(units, lane);
+    uint8_t *exo = units + wave_units_bytes(a.S);                       // [64][32] exit - E
+    uint16_t *cnt = reinterpret_cast<uint16_t *>(exo + 64 * 32);        // [64][32]
+    uint8_t *ent = reinterpret_cast<uint8_t *>(cnt + 64 * 32);          // [64] entry of each lane
+    const uint32_t sh = 32 - g.k1;
+    const uint32_t n = *a.n_pending;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const uint64_t t = a.pending[i];
+        const uint64_t k = (t << 6) + lane;
+        const bool act = k < a.K;
+        __syncthreads();                     // the previous tile is done with the LDS
+        if (wv == 0)
+            load_units(tt_of(units, lane), a.words, k, a.K, wps);
+        __syncthreads();
+        const uint32_t E = lane_end(k, a.K, a.B, a.S);
+        for (uint32_t e = wv; e < g.L && e < 32; e += WPG) {
+            uint32_t ex = e, c = 0;
+            if (act)
+                run_path<PAIR>(TTl, e, E, st, g, sh, ex, c);
+            exo[lane * 32 + e] = static_cast<uint8_t>(ex - E);
+            cnt[lane * 32 + e] = static_cast<uint16_t>(c);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t e = 0;
+            for (uint32_t l = 0; l < 64; ++l) {
+                ent[l] = static_cast<uint8_t>(e);
+                if ((t << 6) + l < a.K)
+                    e = exo[l * 32 + e];
+            }
+            ent[0] = 0;
+            a.rec[t].last_entry = static_cast<uint8_t>(e);
+        }
+        __syncthreads();
+        if (wv == 0) {
+            const uint32_t e = ent[lane];
+            const uint32_t c = act ? cnt[lane * 32 + e] : 0u;
+            if (act)
+                a.gap_s[k] = static_cast<uint8_t>(e);
+            const uint32_t total = static_cast<uint32_t>(wave_sum_u64(c));
+            if (lane == 0)
+                a.tot[t] = total;
+        }
+    }
+}
+
+// LDS of the pending-tile kernel.
+__host__ __device__ __forceinline__ uint32_t pending_lds_bytes(uint32_t k1, uint32_t S)
+{
+    return table_lds_bytes(k1) + wave_units_bytes(S) + 64 * 32 * 3 + 64;
+}
+
+__global__ void k_zero_u32(uint32_t *p)
+{
+    if (threadIdx.x == 0)
+        *p = 0;
 }
 
 template <int WPG, bool PAIR>
@@ -1319,7 +1426,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
             }
             load_units(TTl, a.words, (v << 6) + lane, a.K, wps);
             wave_lds_sync();
-            e = sync_and_store<PAIR>(a, v, TTl, lane, e, false, st, g, sh);
+            e = sync_and_store<PAIR>(a, v, TTl, lane, e, false, kMaxRounds, st, g, sh);
             wave_lds_sync();
         }
     }
@@ -1769,12 +1876,15 @@ struct SyncWs {
     uint8_t *gap_s;
     uint32_t *tot;
     SyncRec *rec;
+    uint32_t *n_pending;
+    uint32_t *pending;
 };
 
 size_t sync_ws_bytes(uint64_t K)
 {
     const uint64_t nt = ceil_div(K, 64);
-    return gap_ws_bytes(nt) + align_up(K, 256) + align_up(4 * nt, 256) + align_up(kSyncRecBytes * nt, 256);
+    return gap_ws_bytes(nt) + align_up(K, 256) + 2 * align_up(4 * nt, 256) + align_up(kSyncRecBytes * nt, 256) +
+           256;
 }
 
 SyncWs sync_ws(void *workspace, uint64_t K)
@@ -1787,6 +1897,10 @@ SyncWs sync_ws(void *workspace, uint64_t K)
     w.tot = reinterpret_cast<uint32_t *>(p);
     p += align_up(4 * nt, 256);
     w.rec = reinterpret_cast<SyncRec *>(p);
+    p += align_up(kSyncRecBytes * nt, 256);
+    w.pending = reinterpret_cast<uint32_t *>(p);
+    p += align_up(4 * nt, 256);
+    w.n_pending = reinterpret_cast<uint32_t *>(p);
     return w;
 }
 
@@ -1799,11 +1913,18 @@ hd_status launch_sync(const SyncArgs &a, uint32_t grid, uint32_t lds, hipStream_
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_sync<WPG, PAIR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
             hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_link<WPG, PAIR>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_pending<WPG, PAIR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
             return HD_ERR_DEVICE;
         attr_set = true;
     }
+    // the pending count is cleared by a kernel (not a memset) so the
+    // sequence can be captured in a graph
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, a.n_pending);
     hipLaunchKernelGGL((k_ss_sync<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
+    hipLaunchKernelGGL((k_ss_pending<WPG, PAIR>), dim3(grid), dim3(WPG * 64),
+                       pending_lds_bytes(a.tab.k1, a.S), stream, a);
     hipLaunchKernelGGL((k_ss_link<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
@@ -1831,6 +1952,8 @@ hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, h
     a.tot = w.tot;
     a.rec = w.rec;
     a.status = status;
+    a.n_pending = w.n_pending;
+    a.pending = w.pending;
     a.tab = view_of(s->table);
     a.B = i.n_bits;
     a.K = i.n_subseq;
