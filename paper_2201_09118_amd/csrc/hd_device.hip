@@ -1030,7 +1030,9 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
     }
 }
 
-// Entries logged per lane by the single-stream decode (pair format, S <= 128).
+// Iterations whose entries the count pass logs per lane (pair format): 24
+// registers; enough for nearly every lane at S = 128, and at larger S the
+// rest of a lane is walked.
 constexpr int kLogIters = 12;
 
 template <bool PAIR, uint32_t MAXU>
@@ -1068,8 +1070,8 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
         const uint64_t c_lo = in.c_lo, c_hi = in.c_hi;
         in.load(sd, t + tstride, ntiles, lane);
         wave_lds_sync();
-        decode_tile<PAIR, (PAIR && MAXU == kSmallUnits) ? kLogIters : 0>(sd, t, lane, gk, gn, c_lo, c_hi, TTl,
-                                                                           stage, dummy, st, g, sh, err);
+        decode_tile<PAIR, PAIR ? kLogIters : 0>(sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, g, sh,
+                                                err);
     }
     if (err)
         atomicOr(a.status, err);
