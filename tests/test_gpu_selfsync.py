@@ -70,6 +70,37 @@ def test_fixed_length_code_never_synchronizes():
     _check_ss(case)
 
 
+@pytest.mark.parametrize("S", [32, 96, 256, 512])
+def test_unconverged_tiles_at_every_subsequence_size(S):
+    """3-bit fixed-length code at several subsequence sizes and a ragged
+    length: tiles stay unconverged after the sync kernel's two rounds and are
+    finished from per-entry exit tables."""
+    rng = np.random.default_rng(30 + S)
+    x = rng.integers(0, 8, 200_003).astype(np.uint16)
+    flush(f"unconverged tiles S={S}")
+    _check_ss(make_case(x, 8, 3, S, 32))
+
+
+def test_runs_of_one_long_codeword_selfsync():
+    """Runs of one long codeword (19 bits: a symbol that is rare overall, as
+    the clamped values at the edge of a Lorenzo field) inside ordinary
+    short-code data: those tiles resynchronize slowly or not at all and walk
+    long codes through the per-length limits."""
+    rng = np.random.default_rng(31)
+    base = hdsynth.two_sided_geometric(rng, 600_000, 0.6, 1024)
+    hist = np.bincount(base, minlength=1024).astype(np.uint64) * 4096
+    hist[0] = 1
+    ln = oracle.code_lengths(hist, 24)
+    cd = oracle.canonical_codes(ln)
+    assert ln[0] == ln.max() and ln[0] >= 16
+    parts = []
+    for seg in np.array_split(base, 25):
+        parts += [seg, np.zeros(int(rng.integers(40, 400)), np.uint16)]
+    x = np.concatenate(parts)
+    flush(f"runs of one long codeword: {x.size} symbols")
+    _check_ss(make_case(x, 1024, 24, 128, 32, ln, cd))
+
+
 def test_even_length_code_odd_entries():
     """All codewords 2 bits: paths from odd offsets never meet even ones."""
     x = np.repeat(np.arange(4, dtype=np.uint16), 20_000)
