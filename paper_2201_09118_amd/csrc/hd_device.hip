@@ -310,6 +310,13 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int)
     return v;
 }
 
+// The wavefront's index in its workgroup, as a wavefront-uniform (scalar)
+// value, so that tile and stream arithmetic derived from it stays scalar.
+__device__ __forceinline__ int wave_index()
+{
+    return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+}
+
 // Lane l's value, the same in every lane.
 __device__ __forceinline__ uint32_t lane_value(uint32_t v, int l)
 {
@@ -745,6 +752,7 @@ struct StreamDev {
     uint64_t n, B, K, M, n_words;
     uint32_t S, stage;           // stage: staging symbols per wave (multiple of 64)
     uint32_t Cl;                 // log2 of the chunk size C (C divides 64)
+    uint32_t last_bits;          // bits of the last subsequence, B - (K - 1) S
 };
 
 // log2 of a chunk size that divides 64 (checked before any launch)
@@ -793,11 +801,10 @@ struct TileInT {
     uint32_t pwn = 0, gk = 0, gn = 0;
     uint64_t c_lo = 0, c_hi = 0;
 
-    // Units of subsequence k (k < K) and the next subsequence's first unit
-    // ((k+1)*S/32 < n_words for k < K).
-    __device__ __forceinline__ void load_words(const uint32_t *words, uint64_t k, uint32_t wps)
+    // The units at src (a subsequence k < K) and the next subsequence's first
+    // unit ((k+1)*S/32 < n_words for k < K).
+    __device__ __forceinline__ void load_words(const uint32_t *src, uint32_t wps)
     {
-        const uint32_t *src = words + k * wps;
         if ((wps & 3) == 0) {
 #pragma unroll
             for (uint32_t i = 0; i < MAXU / 4; ++i)
@@ -817,16 +824,24 @@ struct TileInT {
         pwn = src[wps];
     }
 
+    // Tile t (wavefront-uniform): the tile's bases are scalar, each lane adds
+    // 32-bit offsets (k = 64 t + lane).
     __device__ __forceinline__ void load(const StreamDev &sd, uint64_t t, uint64_t ntiles, int lane)
     {
-        const uint32_t wps = sd.S >> 5;
-        const uint64_t k = (t << 6) + lane;
-        if (t < ntiles && k < sd.K) {
-            load_words(sd.words, k, wps);
-            gk = sd.gap[k];
-            gn = k + 1 < sd.K ? sd.gap[k + 1] : 0u;
-            c_lo = sd.chunk_off[k >> sd.Cl];           // bounds of this lane's chunk
-            c_hi = sd.chunk_off[(k >> sd.Cl) + 1];     // (k / C + 1 <= M for k < K)
+        if (t < ntiles) {
+            const uint32_t wps = sd.S >> 5;
+            const uint64_t k0 = t << 6;
+            const uint64_t left = sd.K - k0;                      // subsequences from k0 on
+            const uint32_t l = static_cast<uint32_t>(lane);
+            if (l < left) {
+                load_words(sd.words + k0 * wps + l * wps, wps);
+                const uint8_t *gb = sd.gap + k0;
+                gk = gb[l];
+                gn = l + 1 < left ? gb[l + 1] : 0u;
+                const uint64_t *cb = sd.chunk_off + (k0 >> sd.Cl);   // C divides 64
+                c_lo = cb[l >> sd.Cl];                  // bounds of this lane's chunk
+                c_hi = cb[(l >> sd.Cl) + 1];            // (k / C + 1 <= M for k < K)
+            }
         }
     }
 
@@ -948,17 +963,15 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
     static_assert(CAP == 0 || PAIR, "the entry log holds pair-format entries");
     const uint32_t S = sd.S;
     const uint32_t PB = sd.stage - 8;
-    const uint64_t k0 = t << 6;
-    const uint64_t k = k0 + lane;
-    const bool act = k < sd.K;
+    const uint64_t k0 = t << 6;                       // wavefront-uniform
+    const uint64_t left = sd.K - k0;                  // subsequences from k0 on (>= 1)
+    const uint32_t l = static_cast<uint32_t>(lane);
+    const bool act = l < left;
+    const bool last = l + 1 == left;                  // the stream's last subsequence
     const uint32_t gk = act ? gk_in : 0u;
 
     // 2. count pass (positions relative to the lane's subsequence start)
-    uint32_t re = 0;
-    if (act) {
-        const uint64_t e = (k + 1) * S < sd.B ? (k + 1) * S : sd.B;
-        re = static_cast<uint32_t>(e - k * S);
-    }
+    const uint32_t re = act ? (last ? sd.last_bits : S) : 0u;
     uint32_t rs = gk;
     if (gk >= 32) {
         err |= kErrGapRange;
@@ -977,7 +990,7 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
         cnt = count_walk<PAIR>(TTl, q, qe, st, g, sh, err);
     // the walk must stop exactly on the next subsequence's start
     if (act) {
-        const uint32_t expect = (k + 1 < sd.K) ? S + gn : re;
+        const uint32_t expect = last ? re : S + gn;
         if (q - 31 != expect)
             err |= kErrLaneEnd;
     }
@@ -991,7 +1004,7 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
     {
         const uint32_t cl = lane & ((1u << sd.Cl) - 1u);
         const uint32_t excl_first = __shfl(excl, lane - cl, 64);
-        if (act && (cl == (1u << sd.Cl) - 1u || k == sd.K - 1)) {
+        if (act && (cl == (1u << sd.Cl) - 1u || last)) {
             if (gbase + excl_first != c_lo || gbase + incl != c_hi)
                 err |= kErrChunkSum;
         }
@@ -1046,7 +1059,7 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 
     const StreamDev &sd = a.sd;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = wave_index();
     const uint32_t wps = sd.S >> 5;
     unsigned char *area = smem + table_lds_bytes(g.k1) + wv * wave_area_bytes(sd.S, sd.stage);
     uint32_t *TTl = tt_of(area, lane);
@@ -1306,7 +1319,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_sync(SyncArgs a)
         *a.status = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = wave_index();
     const uint32_t wps = a.S >> 5;
     uint32_t *TTl = tt_of(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S), lane);
     const uint32_t sh = 32 - g.k1;
@@ -1336,7 +1349,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
     const SmemTable st = carve_table(smem, g.k1);
     load_table(st, g);
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = wave_index();
     const uint32_t wps = a.S >> 5;
     unsigned char *units = smem + table_lds_bytes(g.k1);
     const uint32_t *TTl = tt_of(units, lane);
@@ -1406,7 +1419,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
     load_table(st, g);
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = wave_index();
     const uint32_t wps = a.S >> 5;
     uint32_t *TTl = tt_of(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S), lane);
     const uint32_t sh = 32 - g.k1;
@@ -1487,7 +1500,7 @@ __global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = wave_index();
     unsigned char *area = smem + table_lds_bytes(a.k1_alloc) + wv * wave_area_bytes(a.S_alloc, a.stage_alloc);
     uint32_t *TTl = tt_of(area, lane);
     uint16_t *stage = reinterpret_cast<uint16_t *>(area + wave_units_bytes(a.S_alloc));
@@ -2096,6 +2109,7 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     a.sd.M = M;
     a.sd.n_words = i.n_words;
     a.sd.S = i.subseq_bits;
+    a.sd.last_bits = i.n_subseq ? static_cast<uint32_t>(i.n_bits - (i.n_subseq - 1) * i.subseq_bits) : 0u;
     a.sd.Cl = ss ? 6u : chunk_log2(i.chunk_subseqs);
     a.sd.stage = p.stage;
     a.status = w.status;
@@ -2399,6 +2413,7 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
         b.sd.M = si.n_chunks;
         b.sd.n_words = si.n_words;
         b.sd.S = si.subseq_bits;
+        b.sd.last_bits = si.n_subseq ? static_cast<uint32_t>(si.n_bits - (si.n_subseq - 1) * si.subseq_bits) : 0u;
         b.sd.Cl = chunk_log2(si.chunk_subseqs);
         b.sd.stage = stage[i];
         b.tab = view_of(s.table);
