@@ -633,16 +633,23 @@ template <int CAP>
 __device__ __forceinline__ void replay_log(const uint32_t (&lg)[2 * CAP], uint32_t nlog, uint16_t *dst,
                                            uint32_t cnt, uint16_t *dummy)
 {
+    // A checked store picks between two base addresses (the slot's and one
+    // below the dummy) and keeps its own offset, so the check costs a compare
+    // and a select.
+    uint16_t *const dm1 = dummy - 1;
+    const uint32_t cm1 = cnt - 1;                 // cnt >= 1 whenever nlog >= 1
     uint32_t j = 0;
 #pragma unroll
     for (int i = 0; i < CAP; ++i) {
         if (static_cast<uint32_t>(i) < nlog) {
             const uint32_t e1 = lg[2 * i], e2 = lg[2 * i + 1];
-            dst[j] = static_cast<uint16_t>(e1 & 0xfffu);   // an iteration's first codeword is always the lane's
-            *(j + 1 < cnt ? dst + j + 1 : dummy) = static_cast<uint16_t>((e1 >> 16) & 0xfffu);
+            uint16_t *p = dst + j;
+            p[0] = static_cast<uint16_t>(e1 & 0xfffu);   // an iteration's first codeword is always the lane's
+            (j < cm1 ? p : dm1)[1] = static_cast<uint16_t>((e1 >> 16) & 0xfffu);
             j += 1u + (e1 >= (1u << 28));
-            *(j < cnt ? dst + j : dummy) = static_cast<uint16_t>(e2 & 0xfffu);
-            *(j + 1 < cnt ? dst + j + 1 : dummy) = static_cast<uint16_t>((e2 >> 16) & 0xfffu);
+            p = dst + j;
+            (j < cnt ? p : dm1 + 1)[0] = static_cast<uint16_t>(e2 & 0xfffu);
+            (j < cm1 ? p : dm1)[1] = static_cast<uint16_t>((e2 >> 16) & 0xfffu);
             j += (e2 != 0 ? 1u : 0u) + (e2 >= (1u << 28));
         }
     }
