@@ -6,13 +6,15 @@
 //   2. start at k*S + gap[k] (Sec. III-C) and count the codewords that start
 //      inside the subsequence (the paper's "redundant decoding" to learn
 //      where each thread writes, Sec. IV-C; the chunk totals come from the
-//      stream's chunk_counts, so this pass only spans one subsequence);
+//      stream's chunk_counts, so this pass only spans one subsequence),
+//      keeping the table entries it reads in registers (pair format);
 //   3. wavefront exclusive scan of the counts gives each lane its output
 //      index inside the tile (Sec. III-B, step 3);
-//   4. decode again into an LDS staging tile (Sec. IV-B, Algorithm 1) and
-//      write the tile to HBM with 16-byte coalesced stores; a tile larger
-//      than the staging area is written in several passes, each lane
-//      resuming where it stopped.
+//   4. write the symbols into an LDS staging tile (Sec. IV-B, Algorithm 1)
+//      from the kept entries, or by decoding again, and write the tile to
+//      HBM with 16-byte coalesced stores; a tile larger than the staging
+//      area is written in several passes, each lane resuming where it
+//      stopped.
 // The decode table (first level + per-length canonical limits) lives in LDS
 // for the whole persistent workgroup.
 #include <hip/hip_runtime.h>
@@ -83,7 +85,8 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 //                        longer codeword, kLenBad for a prefix of no
 //                        codeword (for both, the symbol field holds the
 //                        length the per-length search starts at: the
-//                        shortest codeword under that prefix).  Pair format (alphabet <= 4096, k1 <= 12):
+//                        shortest codeword under that prefix).
+//                        Pair format (alphabet <= 4096, k1 <= 12):
 //                        entry = sym1 | (len1 + len2) << 12 | sym2 << 16 |
 //                        len2 << 28, the first codeword and, when it also
 //                        fits in the k1 bits, the one after it (len2 = 0:
@@ -863,7 +866,6 @@ struct TileInT {
         }
     }
 };
-using TileIn = TileInT<kMaxUnitsPerLane>;
 
 // Writes staged output [g0, g1) (global indices; the stage starts at the
 // 16-byte group holding g0): whole 16-byte groups with one 16-byte store per
@@ -1118,8 +1120,11 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 // lockstep with the old one until they meet (the exit stays, the count is
 // re-derived) or the new path leaves the subsequence (a new exit).
 // Rounds end when a wavefront ballot finds no exit changed; after round r
-// lanes 0..r agree with the entry, so at most 64 rounds run, and no budget
-// ever decides the result.
+// lanes 0..r agree with the entry, so at most 64 rounds are ever needed.
+// The sync kernel spends at most kSyncRounds rounds on a tile and lists it
+// otherwise; the pending-tile kernel finishes listed tiles from per-entry
+// exit tables (every lane walked from every entry g < L, then the entries
+// chained from lane 0), so no budget ever decides the result.
 //
 // Step 2 (inter-tile): the entry of tile u is the exit of tile u-1's last
 // lane.  Phase 1 assumes entry 0 and then walks lane 0's subsequence from
