@@ -1218,7 +1218,7 @@ __device__ __forceinline__ void load_units(uint32_t *TTl, const uint32_t *words,
 constexpr uint32_t kMaxRounds = 65;
 // Rounds the main sync kernel spends on a tile before handing it to the
 // pending-tile kernel.
-constexpr uint32_t kSyncRounds = 2;
+constexpr uint32_t kSyncRounds = 4;
 
 // Returns whether the rounds converged within max_rounds.
 template <bool PAIR>
@@ -1950,8 +1950,7 @@ hd_status launch_sync(const SyncArgs &a, uint32_t grid, uint32_t lds, hipStream_
     // sequence can be captured in a graph
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, a.n_pending);
     hipLaunchKernelGGL((k_ss_sync<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
-    // few tiles: one workgroup per CU is plenty (each loads the table)
-    hipLaunchKernelGGL((k_ss_pending<WPG, PAIR>), dim3(std::min<uint32_t>(grid, device_info()->cus)), dim3(WPG * 64),
+    hipLaunchKernelGGL((k_ss_pending<WPG, PAIR>), dim3(grid), dim3(WPG * 64),
                        pending_lds_bytes(a.tab.k1, a.S), stream, a);
     hipLaunchKernelGGL((k_ss_link<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
