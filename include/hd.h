@@ -167,8 +167,11 @@ size_t hd_table_lds_bytes(const hd_table *t);
 
 /*
  * Device workspace bytes hd_decode needs for stream s in mode m (tune may be
- * NULL).  The workspace holds the status word and the output-index scan; it
- * needs no initialization.
+ * NULL).  The workspace holds the status word and the output-index scan
+ * (self-sync mode also: the found sync points, per-tile totals and records,
+ * and the list of tiles finished by the unconverged-tile pass); it needs no
+ * initialization (every counter in it is cleared on the device, by a kernel,
+ * at the start of each call).
  */
 hd_status hd_decode_workspace_size(const hd_dstream *s, hd_mode m, const hd_tune *tune,
                                    size_t *bytes);
