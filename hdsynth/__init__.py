@@ -17,6 +17,7 @@ SeedSequence(seed); sub-streams use SeedSequence.spawn().
 from __future__ import annotations
 
 import math
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -24,8 +25,11 @@ __all__ = [
     "rng_for",
     "two_sided_geometric",
     "config1_symbols",
+    "LorenzoField",
+    "lorenzo_field",
     "lorenzo_field_codes",
     "config2_symbols",
+    "config2_field",
     "config3_symbols",
     "batch_stream_specs",
     "batch_stream_symbols",
@@ -89,16 +93,35 @@ def _smooth_field(shape, n_waves: int, rng: np.random.Generator) -> np.ndarray:
     return f.numpy()
 
 
-def lorenzo_field_codes(shape=(512, 512, 512), seed: int = 2, n_waves: int = 16,
-                        noise_sigma: float = 1e-3, eb: float = 1e-4,
-                        radius: int = 512) -> np.ndarray:
+@dataclass
+class LorenzoField:
+    """A quantized field as an SZ-style compressor leaves it for the decoder.
+
+    codes        uint16[n], C order: Lorenzo residual + radius, 0 = outlier;
+    outlier_idx  uint64[m], ascending flat index of every code-0 position;
+    outlier_val  int32[m], the true residual at each of those positions;
+    field        float32[shape] (the original data) when kept, else None.
+    """
+    shape: tuple
+    eb: float
+    radius: int
+    codes: np.ndarray
+    outlier_idx: np.ndarray
+    outlier_val: np.ndarray
+    field: np.ndarray | None
+
+
+def lorenzo_field(shape=(512, 512, 512), seed: int = 2, n_waves: int = 16,
+                  noise_sigma: float = 1e-3, eb: float = 1e-4, radius: int = 512,
+                  keep_field: bool = False) -> LorenzoField:
     """SZ-style quantization codes of a seeded smooth float32 field.
 
-    field = 16 random plane sinusoids + N(0, noise_sigma^2), float32.
+    field = n_waves random plane sinusoids + N(0, noise_sigma^2), float32.
     q = floor(f / (2 eb) + 1/2) (float64 arithmetic on the float32 values);
     r = 3-D first-order Lorenzo residual of q with zeros outside the grid;
-    code = r + radius when 0 <= r + radius < 2 radius, else 0.
-    Returned flattened in C order (last axis fastest).
+    code = r + radius when 0 <= r + radius < 2 radius, else 0.  Every code-0
+    position (out-of-range residuals, and r = -radius) goes to the outlier
+    list with its true residual.  Flattened in C order (last axis fastest).
     """
     import torch
 
@@ -107,7 +130,10 @@ def lorenzo_field_codes(shape=(512, 512, 512), seed: int = 2, n_waves: int = 16,
     f += rng.standard_normal(f.shape, dtype=np.float32) * np.float32(noise_sigma)
     ft = torch.from_numpy(f)
     q = torch.floor(ft.to(torch.float64) / (2.0 * eb) + 0.5).to(torch.int32)
-    del ft, f
+    del ft
+    if not keep_field:
+        del f
+        f = None
     # Lorenzo residual = product of backward differences along each axis.
     for ax in range(3):
         d = q.clone()
@@ -119,12 +145,27 @@ def lorenzo_field_codes(shape=(512, 512, 512), seed: int = 2, n_waves: int = 16,
         q = d
     code = q + radius
     code[(code < 0) | (code >= 2 * radius)] = 0
-    return code.to(torch.int32).numpy().astype(np.uint16).reshape(-1)
+    codes = code.to(torch.int32).numpy().astype(np.uint16).reshape(-1)
+    idx = np.flatnonzero(codes == 0).astype(np.uint64)
+    val = q.reshape(-1).numpy()[idx.astype(np.int64)].astype(np.int32)
+    return LorenzoField(tuple(int(v) for v in shape), float(eb), int(radius), codes, idx, val, f)
+
+
+def lorenzo_field_codes(shape=(512, 512, 512), seed: int = 2, n_waves: int = 16,
+                        noise_sigma: float = 1e-3, eb: float = 1e-4,
+                        radius: int = 512) -> np.ndarray:
+    """The codes of lorenzo_field (same arguments)."""
+    return lorenzo_field(shape, seed, n_waves, noise_sigma, eb, radius).codes
 
 
 def config2_symbols(seed: int = 2) -> np.ndarray:
     """512^3 = 134,217,728 Lorenzo-residual codes, A = 1024."""
     return lorenzo_field_codes((512, 512, 512), seed=seed)
+
+
+def config2_field(seed: int = 2, keep_field: bool = False) -> LorenzoField:
+    """The 512^3 field behind config2_symbols, with its outliers (eb 1e-4, radius 512)."""
+    return lorenzo_field((512, 512, 512), seed=seed, keep_field=keep_field)
 
 
 def config3_symbols(n: int = 280_000_000, seed: int = 3, A: int = 4096,
