@@ -284,9 +284,51 @@ hd_status hd_decode_status(const void *workspace, void *hip_stream);
  * 1: a window matching no codeword; 2: a subsequence ending off its
  * successor's start; 3: a chunk count mismatch; 4: counts not adding up to
  * n_symbols; 5: an output index outside [0, n_symbols); 6: no consistent
- * self-synchronization point.  Waits for hip_stream first.
+ * self-synchronization point; 7: a code-0 position missing from the outlier
+ * list (hd_lorenzo_reconstruct).  Waits for hip_stream first.
  */
 uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream);
+
+/* ------------------------------------------------------ reconstruction -- */
+
+/*
+ * SZ-style reconstruction of the field behind decoded quantization codes (the
+ * step after Huffman decoding in the cuSZ decompression of Sec. V-C; the
+ * error-bounded scheme of Sec. II-A).  The codes are the first-order 3-D
+ * Lorenzo prediction residuals of the prequantized integer field q, shifted
+ * by radius, with code 0 marking a residual held in the outlier list:
+ *
+ *   r = code - radius, or outlier_val[m] where code == 0 and
+ *       outlier_idx[m] is the position's flat index;
+ *   q(i,j,k) = sum of r over [0,i] x [0,j] x [0,k] (inverse Lorenzo);
+ *   out(i,j,k) = (float)((double)q * (2.0 * eb)).
+ *
+ * codes      device uint16[ni*nj*nk], C order (k fastest): ni planes of nj
+ *            rows of nk values.  2-D fields pass ni = 1, 1-D fields ni = nj = 1.
+ * outlier_idx, outlier_val
+ *            device uint64[n_outliers] strictly ascending flat indices and
+ *            int32 residuals.  Only code-0 positions consult the list; an entry
+ *            at a non-zero code is ignored.  An unsorted list gives unspecified
+ *            values (no access outside the list).  NULL when n_outliers = 0.
+ * out        device float32[ni*nj*nk]; also the kernels' int32 scratch.
+ * q_out      optional device int32[ni*nj*nk] for q itself (NULL to skip).
+ * workspace  device memory of hd_lorenzo_workspace_size(ni, nj, nk) bytes,
+ *            16-byte aligned; its first word is a status word that
+ *            hd_decode_status / hd_decode_status_bits read like a decode's
+ *            (bit 7: a code-0 position missing from the outlier list; its
+ *            value then counts as 0).  The call clears it on the device.
+ *
+ * Every q must fit int32 (partial sums wrap modulo 2^32 and still end exact).
+ * Returns HD_ERR_ARG for NULL buffers, a short or misaligned workspace,
+ * radius 0 or eb not positive and finite; HD_ERR_UNSUPPORTED for nk > 4096.
+ * An empty field (a zero extent) only clears the status word.  Asynchronous
+ * on hip_stream; HD_ERR_DEVICE for launch failures.
+ */
+size_t hd_lorenzo_workspace_size(uint32_t ni, uint32_t nj, uint32_t nk);
+hd_status hd_lorenzo_reconstruct(const uint16_t *codes, uint32_t ni, uint32_t nj, uint32_t nk,
+                                 uint32_t radius, const uint64_t *outlier_idx, const int32_t *outlier_val,
+                                 uint64_t n_outliers, double eb, float *out, int32_t *q_out, void *workspace,
+                                 size_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------- serving -- */
 

@@ -22,6 +22,7 @@ enum : uint32_t {
     kErrTotal = 1u << 4,        // chunk counts do not add up to n_symbols
     kErrOutRange = 1u << 5,     // an output index fell outside [0, n)
     kErrNoSync = 1u << 6,       // self-synchronization found no consistent start
+    kErrNoOutlier = 1u << 7,    // reconstruction: a code-0 position missing from the outlier list
 };
 
 constexpr uint32_t kLenLong = 0;     // first-level entry: codeword longer than lut_bits

@@ -1,0 +1,394 @@
+// SZ-style reconstruction after Huffman decoding, for gfx950.
+//
+// The decoded symbols are quantization codes of a 3-D field (Sec. II-A:
+// error-bounded lossy compression; Sec. V-C measures the whole cuSZ
+// decompression around the decoder).  Each code is a first-order Lorenzo
+// prediction residual of the prequantized integer field q, shifted by a
+// radius, with code 0 marking a residual held in a separate outlier list
+// (ascending flat index + true residual).  Reconstruction:
+//
+//   r(i,j,k) = code - radius, or the listed residual where code == 0;
+//   q(i,j,k) = sum of r over the box [0,i] x [0,j] x [0,k]   (the inverse of
+//              the predictor: an inclusive prefix sum along every axis);
+//   x(i,j,k) = q * 2 eb, the float64 product rounded once to float32.
+//
+// Three kernels, all streaming HBM-bound work (no contraction, no MFMA):
+//
+//   k_lz_plane   one wavefront per block of R consecutive rows of one plane i.
+//                Per row: codes -> residuals (outliers by binary search, only
+//                for code-0 lanes), inclusive scan along k (8 per lane, DPP
+//                across the wave, a scalar carry across 512-wide chunks), and
+//                a running column sum over the block's rows kept in
+//                registers.  The running sums -- the box sum over the block's
+//                rows up to j and over k' <= k -- go to the output buffer as
+//                int32; the block's column totals go to the carry table.
+//   k_lz_carry   one thread per (i, k): exclusive scan of the column totals
+//                over the row blocks of plane i (in place), so each block gets
+//                the sum over all rows above it.
+//   k_lz_depth   one thread per column (j, k): walks i, adds the block carry
+//                to the plane value, accumulates along i and overwrites the
+//                int32 in the output buffer with the dequantized float32 (the
+//                same element, read then written by the same thread).
+//
+// HBM bytes per element: 2 (codes) + 4 + 4 (int32 out, back in) + 4 (float
+// out), plus 3 x 4 / R for the carry table.  Integer arithmetic is modulo
+// 2^32: every q fits int32, so wrapped partial sums still end exact.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "hd.h"
+#include "hd_internal.h"
+
+namespace {
+
+constexpr uint32_t kLzBlock = 256;          // threads per workgroup, every kernel
+constexpr uint32_t kLzChunk = 512;          // k values per wavefront pass (8 per lane)
+constexpr uint32_t kLzMaxChunks = 8;        // rows up to 4096 values
+constexpr uint32_t kLzDepthUnroll = 8;      // planes loaded ahead in k_lz_depth
+constexpr size_t kLzStatusBytes = 256;      // status word, padded
+
+struct LzArgs {
+    const uint16_t *codes;
+    const uint64_t *oidx;
+    const int32_t *oval;
+    uint64_t n_out;
+    uint32_t *status;
+    uint32_t *out;        // int32 partials, then float32 values
+    int32_t *q_out;       // optional
+    uint32_t *carry;      // [ni][nb][nk]
+    uint32_t ni, nj, nk, nb, rows;
+    uint32_t radius;
+    double two_eb;
+};
+
+// Inclusive sum over lanes 0..l of a wavefront (DPP row shifts within each
+// 16-lane row, then the row broadcasts that carry across rows).
+__device__ __forceinline__ uint32_t lz_wave_scan(uint32_t v)
+{
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xa, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xc, 0xf, false));
+    return v;
+}
+
+// The listed residual at flat index e (lower bound over the ascending index
+// list).  Sets *miss when e is absent.
+__device__ __forceinline__ uint32_t lz_outlier(const uint64_t *idx, const int32_t *val, uint64_t n, uint64_t e,
+                                               bool *miss)
+{
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        if (idx[mid] < e)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (lo < n && idx[lo] == e)
+        return static_cast<uint32_t>(val[lo]);
+    *miss = true;
+    return 0;
+}
+
+constexpr uint32_t kLzPad = 0xffffffffu;     // a k past the row: no residual
+
+// Codes of one lane's 8 consecutive k values starting at element e0 (k0 is
+// the first one's k).  VEC: the 8 codes are one aligned 16-byte load.
+template <bool VEC>
+__device__ __forceinline__ void lz_load_codes(const LzArgs &a, uint64_t e0, uint32_t k0, uint32_t c[8])
+{
+    if (VEC) {
+        if (k0 < a.nk) {
+            const uint4 w = *reinterpret_cast<const uint4 *>(a.codes + e0);
+            c[0] = w.x & 0xffffu; c[1] = w.x >> 16;
+            c[2] = w.y & 0xffffu; c[3] = w.y >> 16;
+            c[4] = w.z & 0xffffu; c[5] = w.z >> 16;
+            c[6] = w.w & 0xffffu; c[7] = w.w >> 16;
+        } else {
+#pragma unroll
+            for (int v = 0; v < 8; ++v)
+                c[v] = kLzPad;
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            c[v] = (k0 + v < a.nk) ? a.codes[e0 + v] : kLzPad;
+    }
+}
+
+template <bool VEC>
+__device__ __forceinline__ void lz_store(const LzArgs &a, uint32_t *dst, uint64_t e0, uint32_t k0,
+                                         const uint32_t s[8])
+{
+    if (VEC) {
+        if (k0 < a.nk) {
+            *reinterpret_cast<uint4 *>(dst + e0) = make_uint4(s[0], s[1], s[2], s[3]);
+            *reinterpret_cast<uint4 *>(dst + e0 + 4) = make_uint4(s[4], s[5], s[6], s[7]);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            if (k0 + v < a.nk)
+                dst[e0 + v] = s[v];
+    }
+}
+
+template <uint32_t NCH, bool VEC>
+__global__ void __launch_bounds__(kLzBlock) k_lz_plane(LzArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t w = uint64_t(blockIdx.x) * (kLzBlock / 64) +
+                       static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6)));
+    if (w >= uint64_t(a.ni) * a.nb)
+        return;
+    const uint32_t i = static_cast<uint32_t>(w / a.nb);
+    const uint32_t b = static_cast<uint32_t>(w - uint64_t(i) * a.nb);
+    const uint32_t j0 = b * a.rows;
+    const uint32_t j1 = min(a.nj, j0 + a.rows);
+
+    uint32_t col[NCH][8];
+#pragma unroll
+    for (uint32_t c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            col[c][v] = 0;
+
+    bool miss = false;
+    uint32_t cur[NCH][8];
+    uint64_t row = (uint64_t(i) * a.nj + j0) * a.nk;
+#pragma unroll
+    for (uint32_t c = 0; c < NCH; ++c)
+        lz_load_codes<VEC>(a, row + c * kLzChunk + lane * 8, c * kLzChunk + lane * 8, cur[c]);
+
+    for (uint32_t j = j0; j < j1; ++j) {
+        // the next row's codes are in flight while this row is scanned
+        uint32_t nxt[NCH][8];
+        const uint64_t nrow = row + a.nk;
+        if (j + 1 < j1) {
+#pragma unroll
+            for (uint32_t c = 0; c < NCH; ++c)
+                lz_load_codes<VEC>(a, nrow + c * kLzChunk + lane * 8, c * kLzChunk + lane * 8, nxt[c]);
+        }
+        uint32_t rowsum = 0;                 // wavefront-uniform carry along k
+#pragma unroll
+        for (uint32_t c = 0; c < NCH; ++c) {
+            const uint32_t k0 = c * kLzChunk + lane * 8;
+            const uint64_t e0 = row + k0;
+            // residuals with code 0 taken as -radius first; each code-0
+            // position then adds (listed residual + radius) to its suffix
+            uint32_t s[8];
+            uint32_t run = 0, zmask = 0;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const uint32_t code = cur[c][v];
+                run += code == kLzPad ? 0u : code - a.radius;
+                zmask |= code == 0 ? 1u << v : 0u;
+                s[v] = run;
+            }
+            while (zmask) {
+                const uint32_t v0 = static_cast<uint32_t>(__builtin_ctz(zmask));
+                zmask &= zmask - 1;
+                const uint32_t fix = lz_outlier(a.oidx, a.oval, a.n_out, e0 + v0, &miss) + a.radius;
+#pragma unroll
+                for (uint32_t v = 0; v < 8; ++v)
+                    s[v] += v >= v0 ? fix : 0u;
+                run += fix;
+            }
+            const uint32_t incl = lz_wave_scan(run);
+            const uint32_t base = incl - run + rowsum;
+            rowsum += static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(incl), 63));
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                col[c][v] += s[v] + base;
+                s[v] = col[c][v];
+            }
+            lz_store<VEC>(a, a.out, e0, k0, s);
+        }
+        row = nrow;
+        if (j + 1 < j1) {
+#pragma unroll
+            for (uint32_t c = 0; c < NCH; ++c)
+#pragma unroll
+                for (int v = 0; v < 8; ++v)
+                    cur[c][v] = nxt[c][v];
+        }
+    }
+    if (a.nb > 1) {
+        const uint64_t t0 = (uint64_t(i) * a.nb + b) * a.nk;
+#pragma unroll
+        for (uint32_t c = 0; c < NCH; ++c) {
+            const uint32_t k0 = c * kLzChunk + lane * 8;
+            lz_store<VEC>(a, a.carry, t0 + k0, k0, col[c]);
+        }
+    }
+    if (miss)
+        atomicOr(a.status, hd::kErrNoOutlier);
+}
+
+// Exclusive scan over row blocks of each plane's column totals (in place).
+__global__ void __launch_bounds__(kLzBlock) k_lz_carry(LzArgs a)
+{
+    const uint64_t t = uint64_t(blockIdx.x) * kLzBlock + threadIdx.x;
+    if (t >= uint64_t(a.ni) * a.nk)
+        return;
+    const uint32_t i = static_cast<uint32_t>(t / a.nk);   // t < 2^32 * 4096
+    const uint32_t k = static_cast<uint32_t>(t - uint64_t(i) * a.nk);
+    uint32_t *p = a.carry + uint64_t(i) * a.nb * a.nk + k;
+    uint32_t acc = 0;
+    for (uint32_t b = 0; b < a.nb; ++b) {
+        const uint32_t v = p[uint64_t(b) * a.nk];
+        p[uint64_t(b) * a.nk] = acc;
+        acc += v;
+    }
+}
+
+template <bool CARRY, bool QOUT>
+__global__ void __launch_bounds__(kLzBlock) k_lz_depth(LzArgs a)
+{
+    const uint64_t t = uint64_t(blockIdx.x) * kLzBlock + threadIdx.x;
+    const uint64_t plane = uint64_t(a.nj) * a.nk;
+    if (t >= plane)
+        return;
+    uint32_t j;
+    if (plane <= 0xffffffffu)
+        j = static_cast<uint32_t>(t) / a.nk;
+    else
+        j = static_cast<uint32_t>(t / a.nk);
+    const uint32_t k = static_cast<uint32_t>(t - uint64_t(j) * a.nk);
+    const uint64_t cstride = uint64_t(a.nb) * a.nk;
+    const uint32_t *cp = a.carry + uint64_t(j / a.rows) * a.nk + k;
+    uint32_t acc = 0;
+    for (uint32_t i0 = 0; i0 < a.ni; i0 += kLzDepthUnroll) {
+        uint32_t v[kLzDepthUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kLzDepthUnroll; ++u) {
+            if (i0 + u < a.ni) {
+                v[u] = a.out[uint64_t(i0 + u) * plane + t];
+                if (CARRY)
+                    v[u] += cp[uint64_t(i0 + u) * cstride];
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kLzDepthUnroll; ++u) {
+            if (i0 + u < a.ni) {
+                acc += v[u];
+                const float x = static_cast<float>(static_cast<double>(static_cast<int32_t>(acc)) * a.two_eb);
+                a.out[uint64_t(i0 + u) * plane + t] = __float_as_uint(x);
+                if (QOUT)
+                    a.q_out[uint64_t(i0 + u) * plane + t] = static_cast<int32_t>(acc);
+            }
+        }
+    }
+}
+
+__global__ void k_lz_clear(uint32_t *status)
+{
+    if (threadIdx.x == 0)
+        *status = 0;
+}
+
+// Rows per wavefront block: 32, halved (down to 8) while the plane kernel
+// would have fewer than 4096 wavefronts.
+uint32_t lz_rows(uint32_t ni, uint32_t nj)
+{
+    uint32_t r = 32;
+    while (r > 8 && uint64_t(ni) * ((uint64_t(nj) + r - 1) / r) < 4096)
+        r >>= 1;
+    return r;
+}
+
+size_t lz_ws_bytes(uint32_t ni, uint32_t nj, uint32_t nk)
+{
+    const uint32_t r = lz_rows(ni, nj);
+    const uint64_t nb = (uint64_t(nj) + r - 1) / r;
+    return kLzStatusBytes + (nb > 1 ? size_t(ni) * nb * nk * 4 : 0);
+}
+
+using PlaneKernel = void (*)(LzArgs);
+
+template <bool VEC>
+PlaneKernel plane_kernel(uint32_t nch)
+{
+    switch (nch) {
+    case 1: return k_lz_plane<1, VEC>;
+    case 2: return k_lz_plane<2, VEC>;
+    case 3:
+    case 4: return k_lz_plane<4, VEC>;
+    default: return k_lz_plane<8, VEC>;
+    }
+}
+
+}  // namespace
+
+extern "C" size_t hd_lorenzo_workspace_size(uint32_t ni, uint32_t nj, uint32_t nk)
+{
+    return lz_ws_bytes(ni, nj, nk);
+}
+
+extern "C" hd_status hd_lorenzo_reconstruct(const uint16_t *codes, uint32_t ni, uint32_t nj, uint32_t nk,
+                                            uint32_t radius, const uint64_t *outlier_idx,
+                                            const int32_t *outlier_val, uint64_t n_outliers, double eb,
+                                            float *out, int32_t *q_out, void *workspace, size_t ws_bytes,
+                                            void *hip_stream)
+{
+    const uint64_t n = uint64_t(ni) * nj * nk;
+    if (!workspace || ws_bytes < lz_ws_bytes(ni, nj, nk) || radius == 0 || !(eb > 0.0) || !std::isfinite(eb))
+        return HD_ERR_ARG;
+    if (n > 0 && (!codes || !out))
+        return HD_ERR_ARG;
+    if (n_outliers > 0 && (!outlier_idx || !outlier_val))
+        return HD_ERR_ARG;
+    if (nk > kLzChunk * kLzMaxChunks)
+        return HD_ERR_UNSUPPORTED;
+    if (reinterpret_cast<uintptr_t>(workspace) % 16)
+        return HD_ERR_ARG;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    uint32_t *status = static_cast<uint32_t *>(workspace);
+    hipLaunchKernelGGL(k_lz_clear, dim3(1), dim3(64), 0, stream, status);
+    if (hipGetLastError() != hipSuccess)
+        return HD_ERR_DEVICE;
+    if (n == 0)
+        return HD_OK;
+
+    LzArgs a{};
+    a.codes = codes;
+    a.oidx = outlier_idx;
+    a.oval = outlier_val;
+    a.n_out = n_outliers;
+    a.status = status;
+    a.out = reinterpret_cast<uint32_t *>(out);
+    a.q_out = q_out;
+    a.rows = lz_rows(ni, nj);
+    a.nb = (nj + a.rows - 1) / a.rows;
+    a.carry = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + kLzStatusBytes);
+    a.ni = ni;
+    a.nj = nj;
+    a.nk = nk;
+    a.radius = radius;
+    a.two_eb = 2.0 * eb;
+
+    const bool vec = nk % 8 == 0 && reinterpret_cast<uintptr_t>(codes) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(out) % 16 == 0;
+    const uint32_t nch = (nk + kLzChunk - 1) / kLzChunk;
+    const uint64_t waves = uint64_t(ni) * a.nb;
+    const uint64_t g1 = (waves + kLzBlock / 64 - 1) / (kLzBlock / 64);
+    const uint64_t g2 = (uint64_t(ni) * nk + kLzBlock - 1) / kLzBlock;
+    const uint64_t g3 = (uint64_t(nj) * nk + kLzBlock - 1) / kLzBlock;
+    if (g1 > 0x7fffffffu || g2 > 0x7fffffffu || g3 > 0x7fffffffu)
+        return HD_ERR_UNSUPPORTED;
+
+    hipLaunchKernelGGL(vec ? plane_kernel<true>(nch) : plane_kernel<false>(nch), dim3(uint32_t(g1)),
+                       dim3(kLzBlock), 0, stream, a);
+    if (a.nb > 1)
+        hipLaunchKernelGGL(k_lz_carry, dim3(uint32_t(g2)), dim3(kLzBlock), 0, stream, a);
+    PlaneKernel depth = a.nb > 1 ? (q_out ? k_lz_depth<true, true> : k_lz_depth<true, false>)
+                                 : (q_out ? k_lz_depth<false, true> : k_lz_depth<false, false>);
+    hipLaunchKernelGGL(depth, dim3(uint32_t(g3)), dim3(kLzBlock), 0, stream, a);
+    return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
+}

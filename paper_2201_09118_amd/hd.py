@@ -40,6 +40,9 @@ SIGNATURES = {
     "hd_autotune": (C.c_int, [_vp, C.c_int, _vp, _vp, _sz, _vp, _vp, _vp]),
     "hd_decode_status": (C.c_int, [_vp, _vp]),
     "hd_decode_status_bits": (_u32, [_vp, _vp]),
+    "hd_lorenzo_workspace_size": (_sz, [_u32, _u32, _u32]),
+    "hd_lorenzo_reconstruct": (C.c_int, [_vp, _u32, _u32, _u32, _u32, _vp, _vp, _u64, C.c_double, _vp, _vp, _vp,
+                                         _sz, _vp]),
     "hd_status_str": (C.c_char_p, [C.c_int]),
     "hd_server_create": (C.c_int, [_sz, _u32, _u32, C.POINTER(_vp)]),
     "hd_server_destroy": (None, [_vp]),
@@ -323,6 +326,29 @@ def autotune(ds: DeviceStream, out, workspace=None, mode: int = MODE_GAP, stream
     _check(lib().hd_autotune(C.byref(d), mode, _dev_ptr(out), _dev_ptr(workspace), workspace.numel(),
                              _stream_handle(stream), C.byref(best), C.byref(ms)), "hd_autotune")
     return best, float(ms.value)
+
+
+def lorenzo_workspace_size(shape) -> int:
+    ni, nj, nk = (int(v) for v in shape)
+    return int(lib().hd_lorenzo_workspace_size(ni, nj, nk))
+
+
+def lorenzo_reconstruct(codes, shape, radius: int, outlier_idx, outlier_val, eb: float, out, q_out=None,
+                        workspace=None, stream=None):
+    """Enqueues hd_lorenzo_reconstruct.  codes: uint16-sized device tensor (int16
+    or uint16) of prod(shape) codes; outlier_idx: int64 device tensor of ascending
+    flat indices (or None); outlier_val: int32 device tensor; out: float32 device
+    tensor; q_out: optional int32 device tensor.  Returns the workspace."""
+    ni, nj, nk = (int(v) for v in shape)
+    n_out = 0 if outlier_idx is None else int(outlier_idx.numel())
+    if workspace is None:
+        workspace = alloc_workspace(lorenzo_workspace_size(shape), out.device)
+    _check(lib().hd_lorenzo_reconstruct(_dev_ptr(codes), ni, nj, nk, int(radius),
+                                        _dev_ptr(outlier_idx) if n_out else None,
+                                        _dev_ptr(outlier_val) if n_out else None, n_out, float(eb),
+                                        _dev_ptr(out), _dev_ptr(q_out), _dev_ptr(workspace), workspace.numel(),
+                                        _stream_handle(stream)), "hd_lorenzo_reconstruct")
+    return workspace
 
 
 def decode_status(workspace, stream=None) -> int:
