@@ -30,16 +30,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PROFILE = os.path.join(ROOT, "profiles", "k_decode_gap_config2.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2201_09118_amd", "csrc", "hd_device.hip")
+SZ_PROFILE = os.path.join(ROOT, "profiles", "sz_reconstruct_config2.md")
+SZ_SRC = os.path.join(ROOT, "paper_2201_09118_amd", "csrc", "hd_lorenzo.hip")
 
 
-def measured_traffic():
-    """HBM bytes per decode-kernel launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+def measured_traffic(profile=PROFILE, kernel_src=KERNEL_SRC):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None when the kernel source changed since it was taken."""
     import hashlib
     import re
     try:
-        txt = open(PROFILE).read()
-        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        txt = open(profile).read()
+        src = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
     except OSError:
         return None
     m = re.search(r"traffic_bytes_per_launch: (\d+) \(kernel source sha256 ([0-9a-f]{64})\)", txt)
@@ -354,6 +356,12 @@ def bench_sz(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    if args.calibrate_copy:
+        src = torch.empty(128 << 20, dtype=torch.int16, device=dev).fill_(1)
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {src.numel() * 2} bytes read and written")
+        del src
     tab = hd.Table(ln, cd, L)
     ds = hd.DeviceStream.from_host(hs, tab, device=dev)
     dws = hd.alloc_workspace(hd.decode_workspace_size(ds, hd.MODE_GAP), dev)
@@ -416,8 +424,8 @@ def bench_sz(args):
                                                     "radius 512; codes Huffman-coded with A=1024, L=24, S=128, C=32",
                    "n": n, "outliers": int(F.outlier_idx.size), "n_bits": hs.n_bits},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "hd_lorenzo_reconstruct (k_lz_plane + k_lz_carry + k_lz_depth)",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(SZ_PROFILE, SZ_SRC),
+                     "kernel": "hd_lorenzo_reconstruct (k_lz_plane_ring + k_lz_carry + k_lz_depth)",
                      "kernel_ms": round(rec_ms, 5), "alg_bytes_per_launch": alg},
         "stages_ms": {"decode": round(dec_ms, 5), "reconstruct": round(rec_ms, 5)},
         "decoded_codes_gbs": round(2.0 * n / (dec_ms * 1e-3) / 1e9, 2),

@@ -22,10 +22,12 @@
 //                registers.  The running sums -- the box sum over the block's
 //                rows up to j and over k' <= k -- go to the output buffer as
 //                int32; the block's column totals go to the carry table.
+//                Rows of at most 512 values in whole 16-byte groups take
+//                k_lz_plane_ring, which keeps the next rows' codes in flight.
 //   k_lz_carry   one thread per (i, k): exclusive scan of the column totals
 //                over the row blocks of plane i (in place), so each block gets
 //                the sum over all rows above it.
-//   k_lz_depth   one thread per column (j, k): walks i, adds the block carry
+//   k_lz_depth   one thread per column pair (j, k..k+1): walks i, adds the block carry
 //                to the plane value, accumulates along i and overwrites the
 //                int32 in the output buffer with the dequantized float32 (the
 //                same element, read then written by the same thread).
@@ -47,7 +49,9 @@ namespace {
 constexpr uint32_t kLzBlock = 256;          // threads per workgroup, every kernel
 constexpr uint32_t kLzChunk = 512;          // k values per wavefront pass (8 per lane)
 constexpr uint32_t kLzMaxChunks = 8;        // rows up to 4096 values
-constexpr uint32_t kLzDepthUnroll = 8;      // planes loaded ahead in k_lz_depth
+constexpr uint32_t kLzDepthUnroll = 2;      // planes loaded ahead in k_lz_depth (measured best)
+constexpr int kLzRing = 4;                  // rows in flight in k_lz_plane_ring
+constexpr uint32_t kXcds = 8;               // accelerator complex dies of an MI355X
 constexpr size_t kLzStatusBytes = 256;      // status word, padded
 
 struct LzArgs {
@@ -231,6 +235,83 @@ __global__ void __launch_bounds__(kLzBlock) k_lz_plane(LzArgs a)
         atomicOr(a.status, hd::kErrNoOutlier);
 }
 
+// Rows of at most 512 values in whole 16-byte groups: each lane owns 8
+// consecutive k for the whole block, and the codes of the next PD rows are in
+// flight (a ring of packed 16-byte loads) while a row is scanned.
+template <int PD>
+__global__ void __launch_bounds__(kLzBlock) k_lz_plane_ring(LzArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t w = uint64_t(blockIdx.x) * (kLzBlock / 64) +
+                       static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6)));
+    if (w >= uint64_t(a.ni) * a.nb)
+        return;
+    const uint32_t i = static_cast<uint32_t>(w / a.nb);
+    const uint32_t b = static_cast<uint32_t>(w - uint64_t(i) * a.nb);
+    const uint32_t j0 = b * a.rows;
+    const uint32_t j1 = min(a.nj, j0 + a.rows);
+    const uint32_t k0 = lane * 8;
+    const bool act = k0 < a.nk;
+    const uint64_t base_e = (uint64_t(i) * a.nj + j0) * a.nk + k0;
+
+    uint32_t col[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+        col[v] = 0;
+    bool miss = false;
+    uint4 buf[PD];
+#pragma unroll
+    for (int d = 0; d < PD; ++d)
+        buf[d] = (act && j0 + d < j1) ? *reinterpret_cast<const uint4 *>(a.codes + base_e + uint64_t(d) * a.nk)
+                                      : make_uint4(0, 0, 0, 0);
+    for (uint32_t j = j0; j < j1; j += PD) {
+#pragma unroll
+        for (int d = 0; d < PD; ++d) {
+            if (j + d < j1) {
+                const uint4 wv = buf[d];
+                const uint64_t e0 = base_e + uint64_t(j + d - j0) * a.nk;
+                if (act && j + d + PD < j1)
+                    buf[d] = *reinterpret_cast<const uint4 *>(a.codes + e0 + uint64_t(PD) * a.nk);
+                uint32_t c[8] = {wv.x & 0xffffu, wv.x >> 16, wv.y & 0xffffu, wv.y >> 16,
+                                 wv.z & 0xffffu, wv.z >> 16, wv.w & 0xffffu, wv.w >> 16};
+                uint32_t s[8];
+                uint32_t run = 0, zmask = 0;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    run += act ? c[v] - a.radius : 0u;
+                    zmask |= (act && c[v] == 0) ? 1u << v : 0u;
+                    s[v] = run;
+                }
+                while (zmask) {
+                    const uint32_t v0 = static_cast<uint32_t>(__builtin_ctz(zmask));
+                    zmask &= zmask - 1;
+                    const uint32_t fix = lz_outlier(a.oidx, a.oval, a.n_out, e0 + v0, &miss) + a.radius;
+#pragma unroll
+                    for (uint32_t v = 0; v < 8; ++v)
+                        s[v] += v >= v0 ? fix : 0u;
+                    run += fix;
+                }
+                const uint32_t incl = lz_wave_scan(run);
+                const uint32_t base = incl - run;
+#pragma unroll
+                for (int v = 0; v < 8; ++v)
+                    col[v] += s[v] + base;
+                if (act) {
+                    *reinterpret_cast<uint4 *>(a.out + e0) = make_uint4(col[0], col[1], col[2], col[3]);
+                    *reinterpret_cast<uint4 *>(a.out + e0 + 4) = make_uint4(col[4], col[5], col[6], col[7]);
+                }
+            }
+        }
+    }
+    if (a.nb > 1 && act) {
+        uint32_t *t = a.carry + (uint64_t(i) * a.nb + b) * a.nk + k0;
+        *reinterpret_cast<uint4 *>(t) = make_uint4(col[0], col[1], col[2], col[3]);
+        *reinterpret_cast<uint4 *>(t + 4) = make_uint4(col[4], col[5], col[6], col[7]);
+    }
+    if (miss)
+        atomicOr(a.status, hd::kErrNoOutlier);
+}
+
 // Exclusive scan over row blocks of each plane's column totals (in place).
 __global__ void __launch_bounds__(kLzBlock) k_lz_carry(LzArgs a)
 {
@@ -248,10 +329,26 @@ __global__ void __launch_bounds__(kLzBlock) k_lz_carry(LzArgs a)
     }
 }
 
-template <bool CARRY, bool QOUT>
+template <int N> struct LzVec;
+template <> struct LzVec<1> { using T = uint32_t; };
+template <> struct LzVec<2> { using T = uint2; };
+__device__ __forceinline__ uint32_t &lz_el(uint32_t &v, int) { return v; }
+__device__ __forceinline__ uint32_t &lz_el(uint2 &v, int c) { return c ? v.y : v.x; }
+
+// COLS adjacent columns per thread (COLS = 2 needs an even nk: a pair never
+// straddles two rows).  Planes are loaded kLzDepthUnroll at a time; the
+// final values are written with non-temporal stores (nothing reads them here).
+template <bool CARRY, bool QOUT, int COLS>
 __global__ void __launch_bounds__(kLzBlock) k_lz_depth(LzArgs a)
 {
-    const uint64_t t = uint64_t(blockIdx.x) * kLzBlock + threadIdx.x;
+    using V = typename LzVec<COLS>::T;
+    // Workgroups are dealt to the 8 XCDs round robin; renumber them so that
+    // consecutive rows (which read the same carry-table lines) share one
+    // XCD's L2 instead of fetching each line once per XCD.
+    uint32_t g = blockIdx.x;
+    if (gridDim.x % kXcds == 0)
+        g = (g % kXcds) * (gridDim.x / kXcds) + g / kXcds;
+    const uint64_t t = (uint64_t(g) * kLzBlock + threadIdx.x) * COLS;
     const uint64_t plane = uint64_t(a.nj) * a.nk;
     if (t >= plane)
         return;
@@ -263,25 +360,36 @@ __global__ void __launch_bounds__(kLzBlock) k_lz_depth(LzArgs a)
     const uint32_t k = static_cast<uint32_t>(t - uint64_t(j) * a.nk);
     const uint64_t cstride = uint64_t(a.nb) * a.nk;
     const uint32_t *cp = a.carry + uint64_t(j / a.rows) * a.nk + k;
-    uint32_t acc = 0;
+    uint32_t acc[COLS];
+#pragma unroll
+    for (int c = 0; c < COLS; ++c)
+        acc[c] = 0;
     for (uint32_t i0 = 0; i0 < a.ni; i0 += kLzDepthUnroll) {
-        uint32_t v[kLzDepthUnroll];
+        V v[kLzDepthUnroll];
 #pragma unroll
         for (uint32_t u = 0; u < kLzDepthUnroll; ++u) {
             if (i0 + u < a.ni) {
-                v[u] = a.out[uint64_t(i0 + u) * plane + t];
-                if (CARRY)
-                    v[u] += cp[uint64_t(i0 + u) * cstride];
+                v[u] = *reinterpret_cast<const V *>(a.out + uint64_t(i0 + u) * plane + t);
+                if (CARRY) {
+                    V cv = *reinterpret_cast<const V *>(cp + uint64_t(i0 + u) * cstride);
+#pragma unroll
+                    for (int c = 0; c < COLS; ++c)
+                        lz_el(v[u], c) += lz_el(cv, c);
+                }
             }
         }
 #pragma unroll
         for (uint32_t u = 0; u < kLzDepthUnroll; ++u) {
             if (i0 + u < a.ni) {
-                acc += v[u];
-                const float x = static_cast<float>(static_cast<double>(static_cast<int32_t>(acc)) * a.two_eb);
-                a.out[uint64_t(i0 + u) * plane + t] = __float_as_uint(x);
-                if (QOUT)
-                    a.q_out[uint64_t(i0 + u) * plane + t] = static_cast<int32_t>(acc);
+                const uint64_t e = uint64_t(i0 + u) * plane + t;
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) {
+                    acc[c] += lz_el(v[u], c);
+                    const double x = static_cast<double>(static_cast<int32_t>(acc[c])) * a.two_eb;
+                    __builtin_nontemporal_store(__float_as_uint(static_cast<float>(x)), a.out + e + c);
+                    if (QOUT)
+                        __builtin_nontemporal_store(static_cast<int32_t>(acc[c]), a.q_out + e + c);
+                }
             }
         }
     }
@@ -322,6 +430,13 @@ PlaneKernel plane_kernel(uint32_t nch)
     case 4: return k_lz_plane<4, VEC>;
     default: return k_lz_plane<8, VEC>;
     }
+}
+
+template <int COLS>
+PlaneKernel depth_kernel(bool carry, bool qout)
+{
+    return carry ? (qout ? k_lz_depth<true, true, COLS> : k_lz_depth<true, false, COLS>)
+                 : (qout ? k_lz_depth<false, true, COLS> : k_lz_depth<false, false, COLS>);
 }
 
 }  // namespace
@@ -379,16 +494,19 @@ extern "C" hd_status hd_lorenzo_reconstruct(const uint16_t *codes, uint32_t ni, 
     const uint64_t waves = uint64_t(ni) * a.nb;
     const uint64_t g1 = (waves + kLzBlock / 64 - 1) / (kLzBlock / 64);
     const uint64_t g2 = (uint64_t(ni) * nk + kLzBlock - 1) / kLzBlock;
-    const uint64_t g3 = (uint64_t(nj) * nk + kLzBlock - 1) / kLzBlock;
-    if (g1 > 0x7fffffffu || g2 > 0x7fffffffu || g3 > 0x7fffffffu)
+    if (g1 > 0x7fffffffu || g2 > 0x7fffffffu || (uint64_t(nj) * nk + kLzBlock - 1) / kLzBlock > 0x7fffffffu)
         return HD_ERR_UNSUPPORTED;
 
-    hipLaunchKernelGGL(vec ? plane_kernel<true>(nch) : plane_kernel<false>(nch), dim3(uint32_t(g1)),
-                       dim3(kLzBlock), 0, stream, a);
+    PlaneKernel plane = vec && nch == 1 ? k_lz_plane_ring<kLzRing>
+                                        : vec ? plane_kernel<true>(nch) : plane_kernel<false>(nch);
+    hipLaunchKernelGGL(plane, dim3(uint32_t(g1)), dim3(kLzBlock), 0, stream, a);
     if (a.nb > 1)
         hipLaunchKernelGGL(k_lz_carry, dim3(uint32_t(g2)), dim3(kLzBlock), 0, stream, a);
-    PlaneKernel depth = a.nb > 1 ? (q_out ? k_lz_depth<true, true> : k_lz_depth<true, false>)
-                                 : (q_out ? k_lz_depth<false, true> : k_lz_depth<false, false>);
+    const bool pairs = nk % 2 == 0 && reinterpret_cast<uintptr_t>(out) % 8 == 0 &&
+                       reinterpret_cast<uintptr_t>(q_out) % 8 == 0;
+    PlaneKernel depth = pairs ? depth_kernel<2>(a.nb > 1, q_out != nullptr)
+                              : depth_kernel<1>(a.nb > 1, q_out != nullptr);
+    const uint64_t g3 = (uint64_t(nj) * nk / (pairs ? 2 : 1) + kLzBlock - 1) / kLzBlock;
     hipLaunchKernelGGL(depth, dim3(uint32_t(g3)), dim3(kLzBlock), 0, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
