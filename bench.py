@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["gap", "selfsync", "both"], default="both")
-    ap.add_argument("--workload", choices=["config1", "config2", "config3", "batch", "serve", "sz"], default="config2")
+    ap.add_argument("--workload", choices=["config1", "config2", "config3", "batch", "serve", "sz", "encode"], default="config2")
     ap.add_argument("--batch-streams", type=int, default=256)
     ap.add_argument("--batch-lo", type=int, default=1 << 16)
     ap.add_argument("--batch-hi", type=int, default=1 << 26)
@@ -128,6 +128,8 @@ def main():
         return bench_serve(args)
     if args.workload == "sz":
         return bench_sz(args)
+    if args.workload == "encode":
+        return bench_encode(args)
 
     t0 = time.time()
     w = workload(args.workload)
@@ -435,6 +437,111 @@ def bench_sz(args):
     print(json.dumps(rec), flush=True)
     if not verified:
         sys.exit(1)
+
+
+def bench_encode(args):
+    """Device encoding of the 512^3 config-2 codes (A 1024, L 24, S 128, C 32).
+    One step: device histogram, histogram to the host (8 KiB), codebook on the
+    host, codebook to the device, plan (one host wait for the total bits),
+    write.  value = input GB/s = 2 bytes x n / step time; the device kernels
+    alone (plan + write, codebook fixed) are timed with HIP events too."""
+    import torch
+    import hdsynth
+    import oracle
+    from paper_2201_09118_amd import hd
+
+    x = hdsynth.config2_symbols()
+    n = int(x.size)
+    A, L, S, Cc = 1024, 24, 128, 32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    xs = torch.from_numpy(x.view(np.int16)).to(dev)
+
+    def step():
+        hist = hd.histogram(xs, A, stream=stream).cpu().numpy().astype(np.uint64)
+        ln, cd = hd.build_codebook(hist, L)
+        lnd = torch.from_numpy(ln.astype(np.uint8)).to(dev)
+        cdd = torch.from_numpy(cd.astype(np.uint32).view(np.int32)).to(dev)
+        enc, ws = hd.encode_device(xs, lnd, cdd, L, S, Cc, stream=stream)
+        return enc, ws, ln, cd, lnd, cdd
+
+    enc, ws, ln, cd, lnd, cdd = step()
+    torch.cuda.synchronize()
+    # the oracle packs with the same codebook (the codebook is an input of
+    # the encoder); its histogram + codebook + packing is the CPU baseline
+    t0 = time.perf_counter()
+    oracle_book(x, A, L)
+    e_ref = oracle.encode(x, ln, cd, S, Cc)
+    t_cpu = time.perf_counter() - t0
+    cpu = None if args.no_cpu_baseline else {
+        "value": round(2.0 * n / t_cpu / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+        "sample": f"whole stream ({n} symbols): oracle histogram + codebook + encode, one core, {t_cpu:.2f} s"}
+    ok = (hd.decode_status_bits(ws) == 0 and enc.n_bits == e_ref.n_bits and
+          np.array_equal(enc.words.cpu().numpy().view(np.uint32), e_ref.words) and
+          np.array_equal(enc.gap.cpu().numpy(), e_ref.gap) and
+          np.array_equal(enc.chunk_counts.cpu().numpy().view(np.uint32), e_ref.chunk_counts))
+    log(f"encode verify: {ok}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    # device kernels alone: plan + write into preallocated outputs
+    lay = hd.Layout(S, Cc)
+    K = (enc.n_bits + S - 1) // S
+    M = (K + Cc - 1) // Cc
+    NW = K * S // 32 + 2
+    L_ = hd.lib()
+
+    def kernels():
+        hd._check(L_.hd_encode_plan(hd._dev_ptr(xs), n, hd._dev_ptr(lnd), A, hd._dev_ptr(ws), ws.numel(),
+                                    hd._stream_handle(stream)), "plan")
+        hd._check(L_.hd_encode_write(hd._dev_ptr(xs), n, hd._dev_ptr(lnd), hd._dev_ptr(cdd), A, hd.C.byref(lay),
+                                     hd._dev_ptr(enc.words), NW, hd._dev_ptr(enc.gap), K,
+                                     hd._dev_ptr(enc.chunk_counts), M, hd._dev_ptr(ws), ws.numel(),
+                                     hd._stream_handle(stream)), "write")
+    for _ in range(3):
+        kernels()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in ev:
+        a.record(stream)
+        kernels()
+        b.record(stream)
+    torch.cuda.synchronize()
+    k_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    ok = ok and np.array_equal(enc.words.cpu().numpy().view(np.uint32), e_ref.words)
+    words_bytes = 4 * NW
+    alg = 2 * n + 2 * n + 2 * words_bytes + K + 4 * M     # plan read, write read, zero + write units, gap, counts
+    achieved = alg / (k_ms * 1e-3) / 1e9
+    rec = {
+        "metric": "device Huffman encode GB/s of input symbols (config-2 codes)",
+        "value": round(2.0 * n / (ms_step * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
+        "config": {"workload": "encode", "n_symbols": n, "alphabet": A, "max_len": L, "subseq_bits": S,
+                   "chunk_subseqs": Cc, "n_bits": enc.n_bits,
+                   "step": "histogram + host codebook + plan + host wait + write"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "hd_encode_plan + hd_encode_write", "kernel_ms": round(k_ms, 5),
+                     "alg_bytes_per_launch": alg},
+        "kernels_gbs_input": round(2.0 * n / (k_ms * 1e-3) / 1e9, 2),
+        "cpu_baseline": cpu,
+        "verified": bool(ok),
+    }
+    print(json.dumps(rec), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
+def oracle_book(x, A, L):
+    import oracle
+    ln = oracle.code_lengths(oracle.histogram(x, A), L)
+    return ln, oracle.canonical_codes(ln)
 
 
 def _parallel(fn, items, workers=16):

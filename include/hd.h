@@ -289,6 +289,44 @@ hd_status hd_decode_status(const void *workspace, void *hip_stream);
  */
 uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream);
 
+/* ------------------------------------------------------------ encoding -- */
+
+/*
+ * Device-side encoding into the stream format above: the same words, gap
+ * array (Sec. III-C) and chunk counts as hd_encode_ref, bit for bit.  All
+ * buffers are device memory owned by the caller; calls are asynchronous on
+ * hip_stream except hd_encode_bits.
+ *
+ * hd_histogram: hist[A] (uint64, device) = count of each symbol value < A in
+ *   syms[n]; the call zeroes hist first.  Values >= A are not counted.
+ *   HD_ERR_ARG for A outside [1, 65536] or NULL buffers.
+ * hd_encode_workspace_size: bytes of workspace for n symbols with codes of at
+ *   most L bits under *lay (0 for a bad layout or L outside [1, 32]).
+ * hd_encode_plan: the total codeword bits of syms[n] under lengths[A] (device
+ *   uint8), kept in the workspace; flags a symbol >= A or of length 0.
+ * hd_encode_bits: waits for hip_stream and returns the planned total in
+ *   *n_bits; HD_ERR_SYMBOL when a symbol had no codeword.  The caller sizes
+ *   the outputs from it: n_subseq = ceil(n_bits / S), n_chunks =
+ *   ceil(n_subseq / C), n_words = n_subseq * S / 32 + 2.
+ * hd_encode_write: packs syms[n] with lengths[A] / codes[A] (device, codes
+ *   right-aligned) into words[n_words] (zero-filled by the call, guard units
+ *   included), gap[n_subseq] and chunk_counts[n_chunks].  Needs the plan of
+ *   the same symbols in the same workspace.  HD_ERR_ARG for a bad layout,
+ *   n_chunks != ceil(n_subseq / C), a workspace below
+ *   hd_encode_workspace_size or NULL buffers.  A unit index beyond n_words
+ *   sets status bit 5 (hd_decode_status_bits reads the workspace's status
+ *   word) instead of writing.
+ */
+hd_status hd_histogram(const uint16_t *syms, uint64_t n, uint32_t A, uint64_t *hist, void *hip_stream);
+size_t hd_encode_workspace_size(uint64_t n, uint32_t L, const hd_layout *lay);
+hd_status hd_encode_plan(const uint16_t *syms, uint64_t n, const uint8_t *lengths, uint32_t A, void *workspace,
+                         size_t ws_bytes, void *hip_stream);
+hd_status hd_encode_bits(const void *workspace, uint64_t *n_bits, void *hip_stream);
+hd_status hd_encode_write(const uint16_t *syms, uint64_t n, const uint8_t *lengths, const uint32_t *codes,
+                          uint32_t A, const hd_layout *lay, uint32_t *words, uint64_t n_words, uint8_t *gap,
+                          uint64_t n_subseq, uint32_t *chunk_counts, uint64_t n_chunks, void *workspace,
+                          size_t ws_bytes, void *hip_stream);
+
 /* ------------------------------------------------------ reconstruction -- */
 
 /*

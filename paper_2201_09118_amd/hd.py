@@ -41,6 +41,11 @@ SIGNATURES = {
     "hd_decode_status": (C.c_int, [_vp, _vp]),
     "hd_decode_status_bits": (_u32, [_vp, _vp]),
     "hd_lorenzo_workspace_size": (_sz, [_u32, _u32, _u32]),
+    "hd_histogram": (C.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "hd_encode_workspace_size": (_sz, [_u64, _u32, _vp]),
+    "hd_encode_plan": (C.c_int, [_vp, _u64, _vp, _u32, _vp, _sz, _vp]),
+    "hd_encode_bits": (C.c_int, [_vp, C.POINTER(_u64), _vp]),
+    "hd_encode_write": (C.c_int, [_vp, _u64, _vp, _vp, _u32, _vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _sz, _vp]),
     "hd_lorenzo_reconstruct": (C.c_int, [_vp, _u32, _u32, _u32, _u32, _vp, _vp, _u64, C.c_double, _vp, _vp, _vp,
                                          _sz, _vp]),
     "hd_status_str": (C.c_char_p, [C.c_int]),
@@ -326,6 +331,58 @@ def autotune(ds: DeviceStream, out, workspace=None, mode: int = MODE_GAP, stream
     _check(lib().hd_autotune(C.byref(d), mode, _dev_ptr(out), _dev_ptr(workspace), workspace.numel(),
                              _stream_handle(stream), C.byref(best), C.byref(ms)), "hd_autotune")
     return best, float(ms.value)
+
+
+def histogram(syms, A: int, hist=None, stream=None):
+    """hd_histogram of a uint16-sized device tensor into an int64 device tensor of A bins."""
+    import torch
+    if hist is None:
+        hist = torch.empty(A, dtype=torch.int64, device=syms.device)
+    _check(lib().hd_histogram(_dev_ptr(syms) if syms.numel() else None, syms.numel(), A, _dev_ptr(hist),
+                              _stream_handle(stream)), "hd_histogram")
+    return hist
+
+
+@dataclass
+class DeviceEncoded:
+    words: object
+    gap: object
+    chunk_counts: object
+    n_symbols: int
+    n_bits: int
+    S: int
+    C: int
+
+
+def encode_device(syms, lengths, codes, L: int, S: int = 128, chunk: int = 32, workspace=None, stream=None):
+    """Device encode of a uint16-sized device tensor with a codebook given as
+    device tensors (lengths uint8[A], codes int32[A]): plan, read the total
+    bits (one host wait), allocate, write.  Returns a DeviceEncoded."""
+    import torch
+    n = syms.numel()
+    A = lengths.numel()
+    lay = Layout(S, chunk)
+    if workspace is None:
+        nb = lib().hd_encode_workspace_size(n, L, C.byref(lay))
+        if nb == 0:
+            raise HDError(ERR_ARG, "hd_encode_workspace_size")
+        workspace = alloc_workspace(nb, syms.device)
+    sp = _dev_ptr(syms) if n else None
+    _check(lib().hd_encode_plan(sp, n, _dev_ptr(lengths), A, _dev_ptr(workspace), workspace.numel(),
+                                _stream_handle(stream)), "hd_encode_plan")
+    bits = C.c_uint64()
+    _check(lib().hd_encode_bits(_dev_ptr(workspace), C.byref(bits), _stream_handle(stream)), "hd_encode_bits")
+    B = int(bits.value)
+    K = (B + S - 1) // S
+    M = (K + chunk - 1) // chunk
+    NW = K * S // 32 + 2
+    words = torch.empty(NW, dtype=torch.int32, device=syms.device)
+    gap = torch.empty(max(K, 1), dtype=torch.uint8, device=syms.device)
+    cc = torch.empty(max(M, 1), dtype=torch.int32, device=syms.device)
+    _check(lib().hd_encode_write(sp, n, _dev_ptr(lengths), _dev_ptr(codes), A, C.byref(lay), _dev_ptr(words), NW,
+                                 _dev_ptr(gap), K, _dev_ptr(cc), M, _dev_ptr(workspace), workspace.numel(),
+                                 _stream_handle(stream)), "hd_encode_write")
+    return DeviceEncoded(words, gap[:K], cc[:M], n, B, S, chunk), workspace
 
 
 def lorenzo_workspace_size(shape) -> int:

@@ -1,0 +1,148 @@
+"""GPU parity of the device encoder (hd_histogram, hd_encode_plan / _bits /
+_write) against the CPU oracle's encoder and numpy's bincount.
+
+Integer and byte outputs: words, gap array and chunk counts must equal the
+oracle's bit for bit (tolerance 0)."""
+import numpy as np
+import pytest
+
+import hdsynth
+import oracle
+from hdcase import flush
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2201_09118_amd import hd  # noqa: F401
+    yield
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(dtype)).cuda()
+
+
+def _encode_gpu(x, lengths, codes, L, S, Cc):
+    import torch
+    from paper_2201_09118_amd import hd
+    xs = _dev(x.astype(np.uint16), np.int16) if x.size else torch.empty(0, dtype=torch.int16, device="cuda")
+    enc, ws = hd.encode_device(xs, _dev(lengths.astype(np.uint8), np.uint8), _dev(codes.astype(np.uint32), np.int32),
+                               L, S, Cc)
+    bits = hd.decode_status_bits(ws)
+    torch.cuda.synchronize()
+    return (enc.words.cpu().numpy().view(np.uint32), enc.gap.cpu().numpy(), enc.chunk_counts.cpu().numpy().view(np.uint32),
+            enc.n_bits, bits)
+
+
+def _check(x, lengths, codes, L, S, Cc, tag):
+    flush(f"encode {tag}: n={x.size} S={S} C={Cc} L={L}")
+    e = oracle.encode(x, lengths, codes, S, Cc)
+    w, g, c, B, bits = _encode_gpu(x, lengths, codes, L, S, Cc)
+    assert bits == 0, tag
+    assert B == e.n_bits, tag
+    assert np.array_equal(w, e.words), tag
+    assert np.array_equal(g, e.gap), tag
+    assert np.array_equal(c, e.chunk_counts), tag
+
+
+def _book(x, A, L):
+    ln = oracle.code_lengths(oracle.histogram(x, A), L)
+    return ln, oracle.canonical_codes(ln)
+
+
+@pytest.mark.parametrize("n", [1, 5, 4095, 4096, 4097, 65537, 300_001])
+def test_histogram(n):
+    import torch
+    from paper_2201_09118_amd import hd
+    rng = np.random.default_rng(n)
+    x = hdsynth.two_sided_geometric(rng, n, 0.5, 1024)
+    got = hd.histogram(_dev(x, np.int16), 1024).cpu().numpy()
+    assert np.array_equal(got, np.bincount(x, minlength=1024))
+    # unaligned start (scalar loads) and values >= A ignored
+    xs = _dev(x, np.int16)[1:]
+    got = hd.histogram(xs, 600).cpu().numpy()
+    want = np.bincount(x[1:][x[1:] < 600], minlength=600)
+    assert np.array_equal(got, want)
+    torch.cuda.synchronize()
+
+
+def test_histogram_large_alphabet_global_atomics():
+    from paper_2201_09118_amd import hd
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 65536, size=200_003).astype(np.uint16)
+    got = hd.histogram(_dev(x, np.int16), 65536).cpu().numpy()
+    assert np.array_equal(got, np.bincount(x, minlength=65536))
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 4095, 4096, 4097, 12345, 100_003])
+@pytest.mark.parametrize("S,Cc", [(128, 32), (32, 1), (64, 64), (256, 3)])
+def test_encode_geometric(n, S, Cc):
+    rng = np.random.default_rng(n + S)
+    x = hdsynth.two_sided_geometric(rng, n, 0.6, 1024)
+    ln, cd = _book(x, 1024, 24)
+    _check(x, ln, cd, 24, S, Cc, "geometric")
+
+
+@pytest.mark.parametrize("S", [32, 96, 128])
+def test_encode_32_bit_codewords(S):
+    # lengths 1, 2, ..., 31, 32, 32 (a complete prefix code): many long and
+    # unit-straddling codewords, including 32-bit ones
+    lengths = np.array(list(range(1, 33)) + [32], np.uint8)
+    codes = oracle.canonical_codes(lengths)
+    rng = np.random.default_rng(S)
+    x = rng.integers(0, 33, size=50_001).astype(np.uint16)
+    _check(x, lengths, codes, 32, S, 5, "32-bit codes")
+
+
+def test_encode_config2_full_size_and_decode_back():
+    import torch
+    from paper_2201_09118_amd import hd
+    from hdcase import make_case
+    x = hdsynth.config2_symbols()
+    ln, cd = _book(x, 1024, 24)
+    _check(x, ln, cd, 24, 128, 32, "512^3")
+    # the device-encoded stream decodes back on the device
+    xs = _dev(x, np.int16)
+    enc, _ = hd.encode_device(xs, _dev(ln, np.uint8), _dev(cd.astype(np.uint32), np.int32), 24, 128, 32)
+    info = hd.StreamInfo(x.size, enc.n_bits, enc.words.numel(), enc.gap.numel(), enc.chunk_counts.numel(),
+                         128, 32, 1024, 24)
+    ds = hd.DeviceStream(enc.words, enc.gap, enc.chunk_counts, info, hd.Table(ln, cd, 24))
+    out = torch.empty(x.size, dtype=torch.int16, device="cuda")
+    ws = hd.decode(ds, out, hd.MODE_GAP)
+    assert hd.decode_status_bits(ws) == 0
+    assert torch.equal(out, xs)
+    del make_case
+
+
+def test_symbol_without_codeword_is_reported():
+    from paper_2201_09118_amd import hd
+    x = np.array([0, 1, 2, 3, 2, 1], np.uint16)
+    lengths = np.array([1, 2, 2, 0], np.uint8)        # symbol 3 has no codeword
+    codes = oracle.canonical_codes(lengths)
+    with pytest.raises(hd.HDError) as ei:
+        _encode_gpu(x, lengths, codes, 2, 128, 32)
+    assert ei.value.status == hd.ERR_SYMBOL
+
+
+def test_empty_input():
+    lengths = np.array([1, 1], np.uint8)
+    codes = oracle.canonical_codes(lengths)
+    w, g, c, B, bits = _encode_gpu(np.zeros(0, np.uint16), lengths, codes, 1, 128, 32)
+    e = oracle.encode(np.zeros(0, np.uint16), lengths, codes, 128, 32)
+    assert B == 0 and bits == 0 and np.array_equal(w, e.words) and g.size == e.gap.size and c.size == e.chunk_counts.size
+
+
+def test_bad_layout_rejected():
+    import torch
+    from paper_2201_09118_amd import hd
+    xs = torch.zeros(16, dtype=torch.int16, device="cuda")
+    ln = torch.ones(2, dtype=torch.uint8, device="cuda")
+    cd = torch.zeros(2, dtype=torch.int32, device="cuda")
+    for S, Cc in [(0, 32), (48, 32), (128, 0)]:
+        with pytest.raises(hd.HDError) as ei:
+            hd.encode_device(xs, ln, cd, 1, S, Cc)
+        assert ei.value.status == hd.ERR_ARG
