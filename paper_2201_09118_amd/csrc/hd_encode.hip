@@ -2,17 +2,21 @@
 // stream format read by the decoders (Sec. II-B codewords, Sec. III-B 32-bit
 // units, Sec. III-C gap array, per-chunk codeword counts).
 //
-//   k_enc_hist   histogram of the symbols: per-workgroup counts in LDS, then
-//                one 64-bit atomic add per used bin.
+//   k_enc_hist   histogram of the symbols: a persistent grid, counts in LDS
+//                per workgroup over many blocks, then one 64-bit atomic add
+//                per used bin and workgroup.
 //   k_enc_plan   per block of 4096 symbols, the sum of their code lengths;
-//                flags symbols without a codeword.
+//                flags symbols without a codeword.  (Plan and write stage the
+//                codebook in LDS for alphabets up to 16384.)
 //   k_enc_scan   one workgroup: exclusive scan of the block sums (64-bit
 //                bit offsets) and the stream's total bits.
 //   k_enc_write  per block: each thread takes 16 consecutive symbols, finds
 //                its first bit by a workgroup scan over the block, and packs
-//                its codewords MSB first into 32-bit units.  A unit whose 32
-//                bits all come from one thread is stored; a unit shared with
-//                a neighbour gets an atomic OR (units start zeroed).  A
+//                its codewords MSB first into 32-bit units of an LDS stage
+//                (a unit shared with a neighbour thread is OR-ed there); the
+//                block then stores its units coalesced, with an atomic OR
+//                only on its first and last unit, which it may share with
+//                the neighbour blocks (units start zeroed).  A
 //                symbol whose codeword ends at or past a subsequence boundary
 //                k*S (and starts before it) writes gap[k]; a symbol after
 //                which a chunk boundary falls records itself + 1 as that
@@ -35,7 +39,10 @@ constexpr uint32_t kEncBlock = 256;                    // threads per workgroup
 constexpr uint32_t kEncPer = 16;                       // symbols per thread
 constexpr uint64_t kEncSyms = kEncBlock * kEncPer;     // symbols per block
 constexpr uint32_t kHistLdsBins = 16384;               // LDS histogram up to this alphabet
+constexpr uint32_t kHistGroups = 1024;                 // persistent workgroups of the histogram
+constexpr uint32_t kStageWords = kEncSyms + 2;         // a block's units: <= 4096 x 32 bits, +1 partial
 constexpr size_t kEncHead = 256;                       // status word + total bits
+constexpr uint32_t kTabLdsSyms = 16384;                // codebook in LDS up to this alphabet
 
 struct EncWs {
     uint32_t *status;      // byte 0
@@ -116,6 +123,11 @@ __device__ __forceinline__ void load_syms(const uint16_t *syms, uint64_t n, uint
     }
 }
 
+// A persistent grid: each workgroup counts many blocks of symbols into one
+// LDS histogram and adds it to the global one once, so the global 64-bit
+// atomics (which contend on the few hot bins of a peaked distribution) number
+// workgroups x used bins rather than blocks x used bins.  Alphabets beyond
+// the LDS size count with global atomics directly.
 __global__ void __launch_bounds__(kEncBlock) k_enc_hist(const uint16_t *syms, uint64_t n, uint32_t A,
                                                         unsigned long long *hist, bool vec)
 {
@@ -126,16 +138,19 @@ __global__ void __launch_bounds__(kEncBlock) k_enc_hist(const uint16_t *syms, ui
             h[b] = 0;
         __syncthreads();
     }
-    const uint64_t s0 = (uint64_t(blockIdx.x) * kEncBlock + threadIdx.x) * kEncPer;
-    uint32_t x[kEncPer];
-    load_syms(syms, n, s0, x, vec);
+    const uint64_t nblk = (n + kEncSyms - 1) / kEncSyms;
+    for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const uint64_t s0 = blk * kEncSyms + uint64_t(threadIdx.x) * kEncPer;
+        uint32_t x[kEncPer];
+        load_syms(syms, n, s0, x, vec);
 #pragma unroll
-    for (uint32_t q = 0; q < kEncPer; ++q) {
-        if (x[q] < A) {
-            if (lds)
-                atomicAdd(&h[x[q]], 1u);
-            else
-                atomicAdd(&hist[x[q]], 1ull);
+        for (uint32_t q = 0; q < kEncPer; ++q) {
+            if (x[q] < A) {
+                if (lds)
+                    atomicAdd(&h[x[q]], 1u);
+                else
+                    atomicAdd(&hist[x[q]], 1ull);
+            }
         }
     }
     if (lds) {
@@ -150,6 +165,14 @@ __global__ void __launch_bounds__(kEncBlock) k_enc_plan(const uint16_t *syms, ui
                                                         uint32_t A, uint32_t *block_bits, uint32_t *status, bool vec)
 {
     __shared__ uint32_t lds4[kEncBlock / 64];
+    extern __shared__ uint32_t enc_dyn[];        // lengths (A bytes) when A <= kTabLdsSyms
+    uint8_t *tl = reinterpret_cast<uint8_t *>(enc_dyn);
+    const bool lds = A <= kTabLdsSyms;
+    if (lds) {
+        for (uint32_t b = threadIdx.x; b < A; b += kEncBlock)
+            tl[b] = len[b];
+        __syncthreads();
+    }
     const uint64_t s0 = uint64_t(blockIdx.x) * kEncSyms + uint64_t(threadIdx.x) * kEncPer;
     uint32_t x[kEncPer];
     load_syms(syms, n, s0, x, vec);
@@ -159,7 +182,7 @@ __global__ void __launch_bounds__(kEncBlock) k_enc_plan(const uint16_t *syms, ui
     for (uint32_t q = 0; q < kEncPer; ++q) {
         if (x[q] == 0xffffffffu)
             continue;
-        const uint32_t l = x[q] < A ? len[x[q]] : 0u;
+        const uint32_t l = x[q] < A ? (lds ? tl[x[q]] : len[x[q]]) : 0u;
         bad |= l == 0;
         bits += l;
     }
@@ -232,21 +255,31 @@ struct WriteArgs {
     bool vec;
 };
 
-__device__ __forceinline__ void put_word(const WriteArgs &a, uint64_t w, uint32_t v, bool whole, bool *oob)
+// A unit of the block's LDS stage: stored when this thread owns all of its
+// 32 bits, else OR-ed (the stage starts zeroed).
+__device__ __forceinline__ void put_stage(uint32_t *stage, uint32_t u, uint32_t v, bool whole)
 {
-    if (w >= a.n_words) {
-        *oob = true;
-        return;
-    }
     if (whole)
-        a.words[w] = v;
+        stage[u] = v;
     else if (v)
-        atomicOr(&a.words[w], v);
+        atomicOr(&stage[u], v);
 }
 
 __global__ void __launch_bounds__(kEncBlock) k_enc_write(WriteArgs a)
 {
     __shared__ uint32_t lds4[kEncBlock / 64];
+    __shared__ uint32_t stage[kStageWords];
+    extern __shared__ uint32_t enc_dyn[];        // codes (A words), then lengths (A bytes)
+    uint32_t *tc = enc_dyn;
+    uint8_t *tl = reinterpret_cast<uint8_t *>(enc_dyn + a.A);
+    const bool lds = a.A <= kTabLdsSyms;
+    if (lds) {
+        for (uint32_t b = threadIdx.x; b < a.A; b += kEncBlock) {
+            tc[b] = a.code[b];
+            tl[b] = a.len[b];
+        }
+        __syncthreads();
+    }
     const uint64_t s0 = uint64_t(blockIdx.x) * kEncSyms + uint64_t(threadIdx.x) * kEncPer;
     uint32_t x[kEncPer];
     load_syms(a.syms, a.n, s0, x, a.vec);
@@ -254,7 +287,7 @@ __global__ void __launch_bounds__(kEncBlock) k_enc_write(WriteArgs a)
     uint32_t bits = 0;
 #pragma unroll
     for (uint32_t q = 0; q < kEncPer; ++q) {
-        l[q] = (x[q] < a.A) ? a.len[x[q]] : 0u;
+        l[q] = (x[q] < a.A) ? (lds ? tl[x[q]] : a.len[x[q]]) : 0u;
         bits += l[q];
     }
     uint32_t total;
@@ -262,6 +295,21 @@ __global__ void __launch_bounds__(kEncBlock) k_enc_write(WriteArgs a)
     const uint64_t start = a.block_off[blockIdx.x] + excl;
     const uint64_t n_bits = *a.total;
     bool oob = false;
+
+    // the first subsequence and chunk boundaries after start; each codeword
+    // (at most 32 bits <= S) passes at most one subsequence boundary
+    uint64_t kb = start / a.S + 1;             // next subsequence index
+    uint64_t kbit = kb * a.S;                  // its first bit
+    uint64_t cb = start / a.CS + 1;            // next chunk index
+    uint64_t cbit = cb * a.CS;
+
+    // the block's units go to an LDS stage first: unit 0 of the stage is the
+    // global unit holding the block's first bit
+    const uint64_t bstart = a.block_off[blockIdx.x];
+    const uint64_t u0 = bstart >> 5;
+    for (uint32_t i = threadIdx.x; i < kStageWords; i += kEncBlock)
+        stage[i] = 0;
+    __syncthreads();
 
     // codewords, MSB first: acc holds np pending bits (low bits) that fill
     // unit w from its first bit; the thread's first unit begins with
@@ -275,35 +323,62 @@ __global__ void __launch_bounds__(kEncBlock) k_enc_write(WriteArgs a)
         const uint32_t lq = l[q];
         if (lq == 0)
             continue;
-        const uint32_t c = a.code[x[q]] & (lq == 32 ? 0xffffffffu : ((1u << lq) - 1u));
+        const uint32_t raw = lds ? tc[x[q]] : a.code[x[q]];
+        const uint32_t c = raw & (lq == 32 ? 0xffffffffu : ((1u << lq) - 1u));
         acc = (acc << lq) | c;
         np += lq;
         if (np >= 32) {
             const uint32_t v = static_cast<uint32_t>(acc >> (np - 32));
             // whole unit of this thread when its first bit is not before start
-            put_word(a, w, v, (w << 5) >= start, &oob);
+            put_stage(stage, static_cast<uint32_t>(w - u0), v, (w << 5) >= start);
             ++w;
             np -= 32;
             acc &= np ? ((uint64_t(1) << np) - 1u) : 0u;
         }
-        // gap entry of the subsequence boundary inside (s, s + lq]
         const uint64_t e = s + lq;
-        const uint64_t k = e / a.S;
-        if (k * a.S > s && k < a.K)
-            a.gap[k] = static_cast<uint8_t>(e - k * a.S);
+        // gap entry of the subsequence boundary inside (s, e]
+        if (kbit <= e) {
+            if (kb < a.K)
+                a.gap[kb] = static_cast<uint8_t>(e - kbit);
+            ++kb;
+            kbit += a.S;
+        }
         // chunks whose first codeword is the next one
-        for (uint64_t ch = s / a.CS + 1; ch <= e / a.CS && ch <= a.M; ++ch)
-            a.first[ch] = s0 + q + 1;
+        while (cbit <= e) {
+            if (cb <= a.M)
+                a.first[cb] = s0 + q + 1;
+            ++cb;
+            cbit += a.CS;
+        }
         s = e;
     }
     if (np)
-        put_word(a, w, static_cast<uint32_t>(acc << (32 - np)), false, &oob);
+        put_stage(stage, static_cast<uint32_t>(w - u0), static_cast<uint32_t>(acc << (32 - np)), false);
+    __syncthreads();
+
+    // stage -> HBM: the block's first and last units may hold a neighbour
+    // block's bits too (atomic OR), the ones between are the block's alone
+    if (total) {
+        const uint64_t bend = bstart + total;                 // one past the block's last bit
+        const uint32_t nu = static_cast<uint32_t>(((bend + 31) >> 5) - u0);
+        for (uint32_t i = threadIdx.x; i < nu; i += kEncBlock) {
+            const uint64_t gw = u0 + i;
+            if (gw >= a.n_words) {
+                oob = true;
+                continue;
+            }
+            const bool edge = (i == 0 && (bstart & 31u)) || (i == nu - 1 && (bend & 31u));
+            if (edge)
+                atomicOr(&a.words[gw], stage[i]);
+            else
+                a.words[gw] = stage[i];
+        }
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (a.K)
             a.gap[0] = 0;
         a.first[0] = 0;
-        // chunks past the stream's last codeword start (none when the
-        // layout matches n_bits)
+        // chunks that begin at or after the end of the stream
         for (uint64_t ch = (n_bits ? (n_bits - 1) / a.CS : 0) + 1; ch <= a.M; ++ch)
             if (n_bits == 0 || ch * a.CS >= n_bits)
                 a.first[ch] = a.n;
@@ -353,7 +428,8 @@ extern "C" hd_status hd_histogram(const uint16_t *syms, uint64_t n, uint32_t A, 
                        reinterpret_cast<uint32_t *>(hist), 2 * uint64_t(A));
     if (n) {
         const bool vec = reinterpret_cast<uintptr_t>(syms) % 16 == 0;
-        hipLaunchKernelGGL(k_enc_hist, dim3(grid_of(n, kEncSyms)), dim3(kEncBlock), 0, stream, syms, n, A,
+        const uint32_t g = grid_of(n, kEncSyms) < kHistGroups ? grid_of(n, kEncSyms) : kHistGroups;
+        hipLaunchKernelGGL(k_enc_hist, dim3(g), dim3(kEncBlock), 0, stream, syms, n, A,
                            reinterpret_cast<unsigned long long *>(hist), vec);
     }
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
@@ -371,7 +447,8 @@ extern "C" hd_status hd_encode_plan(const uint16_t *syms, uint64_t n, const uint
     hipLaunchKernelGGL(k_enc_clear, dim3(1), dim3(64), 0, stream, w.status, w.total);
     if (n) {
         const bool vec = reinterpret_cast<uintptr_t>(syms) % 16 == 0;
-        hipLaunchKernelGGL(k_enc_plan, dim3(static_cast<uint32_t>(nblk)), dim3(kEncBlock), 0, stream, syms, n,
+        const size_t lds = A <= kTabLdsSyms ? A : 0;
+        hipLaunchKernelGGL(k_enc_plan, dim3(static_cast<uint32_t>(nblk)), dim3(kEncBlock), lds, stream, syms, n,
                            lengths, A, w.block_bits, w.status, vec);
         hipLaunchKernelGGL(k_enc_scan, dim3(1), dim3(1024), 0, stream, w.block_bits, nblk, w.block_off, w.total);
     }
@@ -426,7 +503,8 @@ extern "C" hd_status hd_encode_write(const uint16_t *syms, uint64_t n, const uin
         a.total = w.total;
         a.status = w.status;
         a.vec = reinterpret_cast<uintptr_t>(syms) % 16 == 0;
-        hipLaunchKernelGGL(k_enc_write, dim3(static_cast<uint32_t>(nblk)), dim3(kEncBlock), 0, stream, a);
+        const size_t lds = A <= kTabLdsSyms ? size_t(A) * 5 : 0;
+        hipLaunchKernelGGL(k_enc_write, dim3(static_cast<uint32_t>(nblk)), dim3(kEncBlock), lds, stream, a);
         if (n_chunks)
             hipLaunchKernelGGL(k_enc_counts, dim3(grid_of(n_chunks, 256)), dim3(256), 0, stream, w.first,
                                n_chunks, chunk_counts);
