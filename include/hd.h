@@ -358,7 +358,8 @@ hd_status hd_encode_write(const uint16_t *syms, uint64_t n, const uint8_t *lengt
  *
  * Every q must fit int32 (partial sums wrap modulo 2^32 and still end exact).
  * Returns HD_ERR_ARG for NULL buffers, a short or misaligned workspace,
- * radius 0 or eb not positive and finite; HD_ERR_UNSUPPORTED for nk > 4096.
+ * radius 0 or eb not positive and finite; HD_ERR_UNSUPPORTED for nk > 4096
+ * unless ni = nj = 1 (a 1-D field of any length up to 2^32 - 1).
  * An empty field (a zero extent) only clears the status word.  Asynchronous
  * on hip_stream; HD_ERR_DEVICE for launch failures.
  */

@@ -33,7 +33,9 @@
 //                same element, read then written by the same thread).
 //
 // HBM bytes per element: 2 (codes) + 4 + 4 (int32 out, back in) + 4 (float
-// out), plus 3 x 4 / R for the carry table.  Integer arithmetic is modulo
+// out), plus 3 x 4 / R for the carry table.  1-D fields longer than 4096
+// values (ni = nj = 1) take a reduce-then-scan over tiles instead: codes read
+// twice, float32 written once (8 bytes per element).  Integer arithmetic is modulo
 // 2^32: every q fits int32, so wrapped partial sums still end exact.
 
 #include <hip/hip_runtime.h>
@@ -395,6 +397,156 @@ __global__ void __launch_bounds__(kLzBlock) k_lz_depth(LzArgs a)
     }
 }
 
+// ---- long 1-D fields (ni = nj = 1, nk > 4096): q is a plain prefix sum of
+// the residuals, done as reduce-then-scan over tiles of 4096 values.
+
+constexpr uint32_t kLzTile = kLzBlock * 16;    // values per tile (16 per thread)
+
+// Residuals of the thread's 16 values starting at element e0 (< n), as
+// inclusive running sums in s[]; returns the thread's total.
+__device__ __forceinline__ uint32_t lz_line_run(const LzArgs &a, uint64_t n, uint64_t e0, bool vec, uint32_t s[16],
+                                                bool *miss)
+{
+    uint32_t c[16];
+    if (vec && e0 + 16 <= n) {
+        const uint4 u = *reinterpret_cast<const uint4 *>(a.codes + e0);
+        const uint4 v = *reinterpret_cast<const uint4 *>(a.codes + e0 + 8);
+        const uint32_t w[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            c[2 * q] = w[q] & 0xffffu;
+            c[2 * q + 1] = w[q] >> 16;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            c[q] = e0 + q < n ? a.codes[e0 + q] : kLzPad;
+    }
+    uint32_t run = 0, zmask = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        run += c[q] == kLzPad ? 0u : c[q] - a.radius;
+        zmask |= c[q] == 0 ? 1u << q : 0u;
+        s[q] = run;
+    }
+    while (zmask) {
+        const uint32_t q0 = static_cast<uint32_t>(__builtin_ctz(zmask));
+        zmask &= zmask - 1;
+        const uint32_t fix = lz_outlier(a.oidx, a.oval, a.n_out, e0 + q0, miss) + a.radius;
+#pragma unroll
+        for (uint32_t q = 0; q < 16; ++q)
+            s[q] += q >= q0 ? fix : 0u;
+        run += fix;
+    }
+    return run;
+}
+
+// Exclusive prefix of v over the 256 threads of the workgroup; *all = total.
+__device__ __forceinline__ uint32_t lz_block_excl(uint32_t v, uint32_t *lds4, uint32_t *all)
+{
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t incl = lz_wave_scan(v);
+    if (lane == 63)
+        lds4[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kLzBlock / 64; ++w) {
+        before += w < wv ? lds4[w] : 0u;
+        tot += lds4[w];
+    }
+    *all = tot;
+    return before + incl - v;
+}
+
+__global__ void __launch_bounds__(kLzBlock) k_lz_line_sum(LzArgs a, uint32_t *tile_sum, bool vec)
+{
+    __shared__ uint32_t lds4[kLzBlock / 64];
+    const uint64_t n = a.nk;
+    const uint64_t e0 = uint64_t(blockIdx.x) * kLzTile + uint64_t(threadIdx.x) * 16;
+    bool miss = false;
+    uint32_t s[16];
+    const uint32_t t = lz_line_run(a, n, e0, vec, s, &miss);
+    uint32_t all;
+    lz_block_excl(t, lds4, &all);
+    if (threadIdx.x == 0)
+        tile_sum[blockIdx.x] = all;
+    if (miss)
+        atomicOr(a.status, hd::kErrNoOutlier);
+}
+
+// One workgroup: exclusive scan of the tile sums, in place (modulo 2^32).
+__global__ void __launch_bounds__(1024) k_lz_line_scan(uint32_t *tile_sum, uint32_t nt)
+{
+    __shared__ uint32_t part[1024 / 64];
+    __shared__ uint32_t carry;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0)
+        carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nt; base += 1024) {
+        const uint32_t b = base + threadIdx.x;
+        const uint32_t v = b < nt ? tile_sum[b] : 0u;
+        const uint32_t incl = lz_wave_scan(v);
+        if (lane == 63)
+            part[wv] = incl;
+        __syncthreads();
+        uint32_t before = carry, all = carry;
+        for (uint32_t w = 0; w < 1024 / 64; ++w) {
+            before += w < wv ? part[w] : 0u;
+            all += part[w];
+        }
+        if (b < nt)
+            tile_sum[b] = before + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            carry = all;
+        __syncthreads();
+    }
+}
+
+template <bool QOUT>
+__global__ void __launch_bounds__(kLzBlock) k_lz_line_out(LzArgs a, const uint32_t *tile_off, bool vec, bool ovec)
+{
+    __shared__ uint32_t lds4[kLzBlock / 64];
+    const uint64_t n = a.nk;
+    const uint64_t e0 = uint64_t(blockIdx.x) * kLzTile + uint64_t(threadIdx.x) * 16;
+    bool miss = false;
+    uint32_t s[16];
+    const uint32_t t = lz_line_run(a, n, e0, vec, s, &miss);
+    uint32_t all;
+    const uint32_t base = lz_block_excl(t, lds4, &all) + tile_off[blockIdx.x];
+    uint32_t f[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        s[q] += base;
+        const double x = static_cast<double>(static_cast<int32_t>(s[q])) * a.two_eb;
+        f[q] = __float_as_uint(static_cast<float>(x));
+    }
+    // a thread's 16 values are 64 contiguous bytes: whole 16-byte stores, so
+    // every line is written in full
+    if (ovec && e0 + 16 <= n) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            *reinterpret_cast<uint4 *>(a.out + e0 + 4 * g) = make_uint4(f[4 * g], f[4 * g + 1], f[4 * g + 2], f[4 * g + 3]);
+            if (QOUT)
+                *reinterpret_cast<uint4 *>(a.q_out + e0 + 4 * g) =
+                    make_uint4(s[4 * g], s[4 * g + 1], s[4 * g + 2], s[4 * g + 3]);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (e0 + q < n) {
+                a.out[e0 + q] = f[q];
+                if (QOUT)
+                    a.q_out[e0 + q] = static_cast<int32_t>(s[q]);
+            }
+        }
+    }
+    if (miss)
+        atomicOr(a.status, hd::kErrNoOutlier);
+}
+
 __global__ void k_lz_clear(uint32_t *status)
 {
     if (threadIdx.x == 0)
@@ -411,8 +563,15 @@ uint32_t lz_rows(uint32_t ni, uint32_t nj)
     return r;
 }
 
+bool lz_line(uint32_t ni, uint32_t nj, uint32_t nk)
+{
+    return ni == 1 && nj == 1 && nk > kLzChunk * kLzMaxChunks;
+}
+
 size_t lz_ws_bytes(uint32_t ni, uint32_t nj, uint32_t nk)
 {
+    if (lz_line(ni, nj, nk))
+        return kLzStatusBytes + (uint64_t(nk) + kLzTile - 1) / kLzTile * 4;
     const uint32_t r = lz_rows(ni, nj);
     const uint64_t nb = (uint64_t(nj) + r - 1) / r;
     return kLzStatusBytes + (nb > 1 ? size_t(ni) * nb * nk * 4 : 0);
@@ -459,7 +618,7 @@ extern "C" hd_status hd_lorenzo_reconstruct(const uint16_t *codes, uint32_t ni, 
         return HD_ERR_ARG;
     if (n_outliers > 0 && (!outlier_idx || !outlier_val))
         return HD_ERR_ARG;
-    if (nk > kLzChunk * kLzMaxChunks)
+    if (nk > kLzChunk * kLzMaxChunks && !lz_line(ni, nj, nk))
         return HD_ERR_UNSUPPORTED;
     if (reinterpret_cast<uintptr_t>(workspace) % 16)
         return HD_ERR_ARG;
@@ -488,6 +647,19 @@ extern "C" hd_status hd_lorenzo_reconstruct(const uint16_t *codes, uint32_t ni, 
     a.radius = radius;
     a.two_eb = 2.0 * eb;
 
+    if (lz_line(ni, nj, nk)) {
+        uint32_t *tiles = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + kLzStatusBytes);
+        const uint32_t nt = static_cast<uint32_t>((uint64_t(nk) + kLzTile - 1) / kLzTile);
+        const bool lvec = reinterpret_cast<uintptr_t>(codes) % 16 == 0;
+        const bool ovec = reinterpret_cast<uintptr_t>(out) % 16 == 0 && reinterpret_cast<uintptr_t>(q_out) % 16 == 0;
+        hipLaunchKernelGGL(k_lz_line_sum, dim3(nt), dim3(kLzBlock), 0, stream, a, tiles, lvec);
+        hipLaunchKernelGGL(k_lz_line_scan, dim3(1), dim3(1024), 0, stream, tiles, nt);
+        if (q_out)
+            hipLaunchKernelGGL(k_lz_line_out<true>, dim3(nt), dim3(kLzBlock), 0, stream, a, tiles, lvec, ovec);
+        else
+            hipLaunchKernelGGL(k_lz_line_out<false>, dim3(nt), dim3(kLzBlock), 0, stream, a, tiles, lvec, ovec);
+        return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
+    }
     const bool vec = nk % 8 == 0 && reinterpret_cast<uintptr_t>(codes) % 16 == 0 &&
                      reinterpret_cast<uintptr_t>(out) % 16 == 0;
     const uint32_t nch = (nk + kLzChunk - 1) / kLzChunk;

@@ -87,6 +87,30 @@ def test_generator_fields(shape):
     _check_field(_more_outliers(F, 0.02, sum(shape)), "mixed")
 
 
+@pytest.mark.parametrize("n", [4097, 8192, 100_003, (1 << 20) + 7])
+def test_long_1d_fields(n):
+    # ni = nj = 1 beyond one wavefront's row: reduce-then-scan over tiles
+    F = hdsynth.lorenzo_field((1, 1, n), seed=n % 97, n_waves=2, noise_sigma=1e-3, eb=1e-3, radius=512)
+    _check_field(_more_outliers(F, 0.01, n), "1-D")
+
+
+def test_long_1d_unaligned_codes():
+    import torch
+    from paper_2201_09118_amd import hd
+    F = hdsynth.lorenzo_field((1, 1, 50_001), seed=7, n_waves=2, noise_sigma=1e-3, eb=1e-3, radius=512)
+    F = _more_outliers(F, 0.02, 7)
+    q_ref, x_ref = sz.reconstruct(F.codes, F.shape, F.radius, F.outlier_idx, F.outlier_val, F.eb)
+    buf = torch.from_numpy(np.concatenate([[0], F.codes]).astype(np.uint16).view(np.int16)).cuda()
+    out = torch.empty(F.codes.size, dtype=torch.float32, device="cuda")
+    q = torch.empty(F.codes.size, dtype=torch.int32, device="cuda")
+    oi = torch.from_numpy(F.outlier_idx.view(np.int64)).cuda()
+    ov = torch.from_numpy(F.outlier_val).cuda()
+    ws = hd.lorenzo_reconstruct(buf[1:], F.shape, F.radius, oi, ov, F.eb, out, q)
+    assert hd.decode_status_bits(ws) == 0
+    assert np.array_equal(q.cpu().numpy(), q_ref.reshape(-1))
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), x_ref.reshape(-1).view(np.uint32))
+
+
 def test_every_code_an_outlier():
     F = hdsynth.lorenzo_field((6, 50, 136), seed=8, n_waves=4, noise_sigma=1e-2, eb=1e-4, radius=4)
     assert F.outlier_idx.size > 0.95 * F.codes.size
@@ -150,7 +174,7 @@ def test_argument_errors():
     out = torch.zeros(64, dtype=torch.float32, device="cuda")
     ws = hd.alloc_workspace(hd.lorenzo_workspace_size((1, 1, 64)))
     for kw, st in [(dict(radius=0), hd.ERR_ARG), (dict(eb=0.0), hd.ERR_ARG), (dict(eb=float("inf")), hd.ERR_ARG),
-                   (dict(shape=(1, 1, 8192)), hd.ERR_UNSUPPORTED)]:
+                   (dict(shape=(2, 1, 8192)), hd.ERR_UNSUPPORTED)]:
         args = dict(shape=(1, 1, 64), radius=512, eb=1e-4)
         args.update(kw)
         with pytest.raises(hd.HDError) as ei:
