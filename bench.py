@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["gap", "selfsync", "both"], default="both")
-    ap.add_argument("--workload", choices=["config1", "config2", "config3", "batch", "serve", "sz", "encode"], default="config2")
+    ap.add_argument("--workload", choices=["config1", "config2", "config3", "batch", "serve", "sz", "sz1d", "encode"], default="config2")
     ap.add_argument("--batch-streams", type=int, default=256)
     ap.add_argument("--batch-lo", type=int, default=1 << 16)
     ap.add_argument("--batch-hi", type=int, default=1 << 26)
@@ -130,6 +130,8 @@ def main():
         return bench_sz(args)
     if args.workload == "encode":
         return bench_encode(args)
+    if args.workload == "sz1d":
+        return bench_sz1d(args)
 
     t0 = time.time()
     w = workload(args.workload)
@@ -567,6 +569,76 @@ def bench_encode(args):
         "verified": bool(ok),
     }
     print(json.dumps(rec), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
+def bench_sz1d(args):
+    """Reconstruction of a 1-D field of 280,000,000 points (the HACC-sized
+    shape): codes = seeded uniform residuals in [-7, 8) + 512 with 0.01% code-0
+    outliers (uniform residuals in [-3000, 3000)), eb 1e-4.  value = float32
+    dataset GB/s of hd_lorenzo_reconstruct alone (inputs resident)."""
+    import torch
+    from oracle import sz
+    from paper_2201_09118_amd import hd
+
+    n = 280_000_000
+    rng = np.random.default_rng(11)
+    codes = rng.integers(505, 520, size=n).astype(np.uint16)
+    z = np.flatnonzero(rng.random(n) < 1e-4)
+    codes[z] = 0
+    oidx = z.astype(np.uint64)
+    oval = rng.integers(-3000, 3000, size=z.size).astype(np.int32)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    c = torch.from_numpy(codes.view(np.int16)).to(dev)
+    oi = torch.from_numpy(oidx.view(np.int64)).to(dev)
+    ov = torch.from_numpy(oval).to(dev)
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    ws = hd.alloc_workspace(hd.lorenzo_workspace_size((1, 1, n)), dev)
+
+    def rec():
+        hd.lorenzo_reconstruct(c, (1, 1, n), 512, oi, ov, 1e-4, out, None, ws, stream)
+
+    rec()
+    t0 = time.perf_counter()
+    _, x_ref = sz.reconstruct(codes, (1, 1, n), 512, oidx, oval, 1e-4)
+    t_cpu = time.perf_counter() - t0
+    ok = hd.decode_status(ws, stream) == hd.OK and bool(
+        np.array_equal(out.cpu().numpy().view(np.uint32), x_ref.reshape(-1).view(np.uint32)))
+    del x_ref
+    for _ in range(args.warmup):
+        rec()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for a, b in ev:
+        a.record(stream)
+        rec()
+        b.record(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    alg = 2 * n + 4 * n + 12 * int(z.size)           # codes in, float32 out, outlier list
+    rec_line = {
+        "metric": "1-D reconstruction GB/s (float32 dataset bytes), 280M points",
+        "value": round(4.0 * n / (ms_step * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u16->i32->f32", "data": "synthetic",
+        "config": {"workload": "sz1d", "n": n, "outliers": int(z.size), "radius": 512, "eb": 1e-4},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (k_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "hd_lorenzo_reconstruct (k_lz_line_sum + k_lz_line_scan + k_lz_line_out)",
+                     "kernel_ms": round(k_ms, 5), "alg_bytes_per_launch": alg},
+        "cpu_baseline": None if args.no_cpu_baseline else {
+            "value": round(4.0 * n / t_cpu / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole field: numpy reconstruction on one core, {t_cpu:.2f} s"},
+        "verified": ok,
+    }
+    print(json.dumps(rec_line), flush=True)
     if not ok:
         sys.exit(1)
 
