@@ -137,3 +137,58 @@ def test_encode_ref_edge_cases():
     assert np.array_equal(hs.words, e.words) and np.array_equal(hs.gap, e.gap)
     assert np.array_equal(hs.chunk_counts, e.chunk_counts)
     assert np.array_equal(oracle.decode(hs.words, hs.n_bits, x.size, ln2, cd2), x)
+
+
+def test_reconstruction_workspace_sizes():
+    # status word (256 B) + the carry table of the three-pass path: ni x (nj / R) x nk int32,
+    # R = 32 rows per wavefront block (halved down to 8 while a field gives < 4096 wavefronts)
+    from paper_2201_09118_amd import hd
+    assert hd.lorenzo_workspace_size((512, 512, 512)) == 256 + 512 * 16 * 512 * 4
+    assert hd.lorenzo_workspace_size((64, 64, 64)) == 256 + 64 * 8 * 64 * 4          # R = 8
+    assert hd.lorenzo_workspace_size((4, 8, 100)) == 256                              # one block: no table
+    # long 1-D fields: one uint32 per tile of 4096 values
+    assert hd.lorenzo_workspace_size((1, 1, 280_000_000)) == 256 + (280_000_000 + 4095) // 4096 * 4
+    assert hd.lorenzo_workspace_size((1, 1, 4096)) == 256
+    assert hd.lorenzo_workspace_size((0, 5, 5)) == 256
+
+
+def test_reconstruction_argument_errors_before_any_launch():
+    from paper_2201_09118_amd import hd
+    f = hd.lib().hd_lorenzo_reconstruct
+    dummy = ctypes.c_void_p(16)                        # never dereferenced: every call fails its checks
+    # no workspace / short workspace / radius 0 / eb <= 0 / NaN eb
+    assert f(dummy, 2, 2, 2, 512, None, None, 0, 1e-4, dummy, None, None, 0, None) == hd.ERR_ARG
+    assert f(dummy, 2, 2, 2, 512, None, None, 0, 1e-4, dummy, None, dummy, 8, None) == hd.ERR_ARG
+    assert f(dummy, 2, 2, 2, 0, None, None, 0, 1e-4, dummy, None, dummy, 256, None) == hd.ERR_ARG
+    assert f(dummy, 2, 2, 2, 512, None, None, 0, 0.0, dummy, None, dummy, 256, None) == hd.ERR_ARG
+    assert f(dummy, 2, 2, 2, 512, None, None, 0, float("nan"), dummy, None, dummy, 256, None) == hd.ERR_ARG
+    # outliers announced without lists; NULL codes
+    assert f(dummy, 2, 2, 2, 512, None, None, 3, 1e-4, dummy, None, dummy, 256, None) == hd.ERR_ARG
+    assert f(None, 2, 2, 2, 512, None, None, 0, 1e-4, dummy, None, dummy, 256, None) == hd.ERR_ARG
+    # rows beyond 4096 values in a 2-D/3-D field
+    ws = hd.lib().hd_lorenzo_workspace_size(2, 1, 8192)
+    assert f(dummy, 2, 1, 8192, 512, None, None, 0, 1e-4, dummy, None, dummy, ws, None) == hd.ERR_UNSUPPORTED
+
+
+def test_encode_workspace_sizes_and_layout_errors():
+    from paper_2201_09118_amd import hd
+    L = hd.lib()
+    lay = hd.Layout(128, 32)
+    n = 134_217_728
+    nblk = (n + 4095) // 4096
+    k_max = (n * 24 + 127) // 128
+    m_max = (k_max + 31) // 32
+    assert L.hd_encode_workspace_size(n, 24, ctypes.byref(lay)) == 256 + nblk * 4 + nblk * 8 + (m_max + 1) * 8
+    assert L.hd_encode_workspace_size(n, 0, ctypes.byref(lay)) == 0
+    assert L.hd_encode_workspace_size(n, 33, ctypes.byref(lay)) == 0
+    assert L.hd_encode_workspace_size(n, 24, ctypes.byref(hd.Layout(0, 32))) == 0
+    assert L.hd_encode_workspace_size(n, 24, None) == 0
+    dummy = ctypes.c_void_p(16)
+    # write: bad layouts and inconsistent chunk counts fail before any launch
+    for S, C_, K, M in [(48, 32, 10, 1), (128, 0, 10, 1), (128, 32, 100, 2), (128, 32, 100, 5)]:
+        st = L.hd_encode_write(dummy, 10, dummy, dummy, 4, ctypes.byref(hd.Layout(S, C_)), dummy, 500, dummy, K,
+                               dummy, M, dummy, 1 << 20, None)
+        assert st == hd.ERR_ARG, (S, C_, K, M)
+    # histogram: alphabet outside [1, 65536]
+    assert L.hd_histogram(dummy, 10, 0, dummy, None) == hd.ERR_ARG
+    assert L.hd_histogram(dummy, 10, 65537, dummy, None) == hd.ERR_ARG
