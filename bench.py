@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["gap", "selfsync", "both"], default="both")
-    ap.add_argument("--workload", choices=["config1", "config2", "config3", "batch", "serve", "sz", "sz1d", "encode"], default="config2")
+    ap.add_argument("--workload", choices=["config1", "config2", "config3", "batch", "serve", "sz", "sz1d", "encode", "lds_sweep"], default="config2")
     ap.add_argument("--batch-streams", type=int, default=256)
     ap.add_argument("--batch-lo", type=int, default=1 << 16)
     ap.add_argument("--batch-hi", type=int, default=1 << 26)
@@ -132,6 +132,8 @@ def main():
         return bench_encode(args)
     if args.workload == "sz1d":
         return bench_sz1d(args)
+    if args.workload == "lds_sweep":
+        return bench_lds_sweep(args)
 
     t0 = time.time()
     w = workload(args.workload)
@@ -640,6 +642,81 @@ def bench_sz1d(args):
     }
     print(json.dumps(rec_line), flush=True)
     if not ok:
+        sys.exit(1)
+
+
+def bench_lds_sweep(args):
+    """Tuned vs brute-force decode parameters on the config-2 stream (the
+    analog of the paper's Table I): hd_decode_run timed for every LDS staging
+    size (256, 512, 1024..8192 in steps of 512, 12288, 16384 symbols per
+    wavefront) times waves per workgroup (occupancy choice, 4, 8, 12, 16),
+    against hd_autotune's pick and the library default."""
+    import torch
+    import hdsynth
+    from paper_2201_09118_amd import hd
+
+    x = hdsynth.config2_symbols()
+    n = int(x.size)
+    ln, cd = hd.build_codebook(np.bincount(x, minlength=1024).astype(np.uint64), 24)
+    hs = hd.encode_ref(x, ln, cd, 24, 128, 32)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    tab = hd.Table(ln, cd, 24)
+    ds = hd.DeviceStream.from_host(hs, tab, device=dev)
+    out = torch.empty(n, dtype=torch.int16, device=dev)
+    xs = torch.from_numpy(x.view(np.int16)).to(dev)
+
+    def time_run(tune, reps=5):
+        ws = hd.alloc_workspace(hd.decode_workspace_size(ds, hd.MODE_GAP, tune), dev)
+        hd.decode_prepare(ds, ws, hd.MODE_GAP, tune, stream)
+        hd.decode_run(ds, out, ws, hd.MODE_GAP, tune, stream)
+        torch.cuda.synchronize()
+        ok = hd.decode_status(ws, stream) == hd.OK and torch.equal(out, xs)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            hd.decode_run(ds, out, ws, hd.MODE_GAP, tune, stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev])), ok
+
+    stages = [256, 512] + list(range(1024, 8193, 512)) + [12288, 16384]
+    grid = {}
+    all_ok = True
+    for w in (0, 4, 8, 12, 16):
+        for st in stages:
+            try:
+                ms, ok = time_run(hd.Tune(w, st, 0, 0))
+            except hd.HDError:
+                continue                            # layout beyond a workgroup's LDS
+            all_ok &= ok
+            grid[f"wpg{w}-stage{st}"] = round(ms, 5)
+    best_key = min(grid, key=grid.get)
+    default_ms, ok = time_run(hd.Tune(0, 0, 0, 0))
+    all_ok &= ok
+    t0 = time.perf_counter()
+    tuned, _ = hd.autotune(ds, out)
+    tune_s = time.perf_counter() - t0
+    tuned_ms, ok = time_run(tuned)
+    all_ok &= ok
+    log(f"sweep best {best_key} {grid[best_key]:.4f} ms; autotune wpg{tuned.waves_per_group}-stage"
+        f"{tuned.stage_symbols} {tuned_ms:.4f} ms (tuning {tune_s * 1e3:.1f} ms); default {default_ms:.4f} ms")
+    rec = {
+        "metric": "decode_run ms on config 2: autotuned vs brute-force LDS staging sweep (Table I analog)",
+        "value": round(tuned_ms, 5), "unit": "ms", "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": round(tuned_ms, 5),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
+        "config": {"workload": "lds_sweep", "n_symbols": n, "settings_swept": len(grid)},
+        "sweep_best": {"setting": best_key, "ms": grid[best_key]},
+        "autotuned": {"setting": f"wpg{tuned.waves_per_group}-stage{tuned.stage_symbols}", "ms": round(tuned_ms, 5),
+                      "vs_sweep_best": round(tuned_ms / grid[best_key] - 1.0, 4),
+                      "tuning_wall_ms": round(tune_s * 1e3, 1)},
+        "default": {"ms": round(default_ms, 5), "vs_sweep_best": round(default_ms / grid[best_key] - 1.0, 4)},
+        "sweep_ms": grid,
+        "verified": bool(all_ok),
+    }
+    print(json.dumps(rec), flush=True)
+    if not all_ok:
         sys.exit(1)
 
 
