@@ -475,38 +475,64 @@ __global__ void __launch_bounds__(kLzBlock) k_lz_line_sum(LzArgs a, uint32_t *ti
         atomicOr(a.status, hd::kErrNoOutlier);
 }
 
-// One workgroup: exclusive scan of the tile sums, in place (modulo 2^32).
-__global__ void __launch_bounds__(1024) k_lz_line_scan(uint32_t *tile_sum, uint32_t nt)
+// Tile sums -> exclusive tile offsets in two levels: each 1024-thread
+// workgroup scans 1024 tile sums in place and leaves its total in group[g];
+// then one workgroup scans the group totals in place (all modulo 2^32).
+constexpr uint32_t kLzScanGroup = 1024;
+
+__device__ __forceinline__ uint32_t lz_group_excl(uint32_t v, uint32_t *part, uint32_t *all)
 {
-    __shared__ uint32_t part[1024 / 64];
-    __shared__ uint32_t carry;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t incl = lz_wave_scan(v);
+    if (lane == 63)
+        part[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (uint32_t w = 0; w < kLzScanGroup / 64; ++w) {
+        before += w < wv ? part[w] : 0u;
+        tot += part[w];
+    }
+    *all = tot;
+    return before + incl - v;
+}
+
+__global__ void __launch_bounds__(kLzScanGroup) k_lz_line_scan(uint32_t *tile_sum, uint32_t nt, uint32_t *group)
+{
+    __shared__ uint32_t part[kLzScanGroup / 64];
+    const uint32_t b = blockIdx.x * kLzScanGroup + threadIdx.x;
+    const uint32_t v = b < nt ? tile_sum[b] : 0u;
+    uint32_t all;
+    const uint32_t ex = lz_group_excl(v, part, &all);
+    if (b < nt)
+        tile_sum[b] = ex;
+    if (threadIdx.x == 0)
+        group[blockIdx.x] = all;
+}
+
+__global__ void __launch_bounds__(kLzScanGroup) k_lz_line_top(uint32_t *group, uint32_t ng)
+{
+    __shared__ uint32_t part[kLzScanGroup / 64];
+    __shared__ uint32_t carry;
     if (threadIdx.x == 0)
         carry = 0;
     __syncthreads();
-    for (uint32_t base = 0; base < nt; base += 1024) {
+    for (uint32_t base = 0; base < ng; base += kLzScanGroup) {
         const uint32_t b = base + threadIdx.x;
-        const uint32_t v = b < nt ? tile_sum[b] : 0u;
-        const uint32_t incl = lz_wave_scan(v);
-        if (lane == 63)
-            part[wv] = incl;
-        __syncthreads();
-        uint32_t before = carry, all = carry;
-        for (uint32_t w = 0; w < 1024 / 64; ++w) {
-            before += w < wv ? part[w] : 0u;
-            all += part[w];
-        }
-        if (b < nt)
-            tile_sum[b] = before + incl - v;
+        const uint32_t v = b < ng ? group[b] : 0u;
+        uint32_t all;
+        const uint32_t ex = lz_group_excl(v, part, &all);
+        if (b < ng)
+            group[b] = carry + ex;
         __syncthreads();
         if (threadIdx.x == 0)
-            carry = all;
+            carry += all;
         __syncthreads();
     }
 }
 
 template <bool QOUT>
-__global__ void __launch_bounds__(kLzBlock) k_lz_line_out(LzArgs a, const uint32_t *tile_off, bool vec, bool ovec)
+__global__ void __launch_bounds__(kLzBlock) k_lz_line_out(LzArgs a, const uint32_t *tile_off, const uint32_t *group,
+                                                           bool vec, bool ovec)
 {
     __shared__ uint32_t lds4[kLzBlock / 64];
     const uint64_t n = a.nk;
@@ -515,7 +541,7 @@ __global__ void __launch_bounds__(kLzBlock) k_lz_line_out(LzArgs a, const uint32
     uint32_t s[16];
     const uint32_t t = lz_line_run(a, n, e0, vec, s, &miss);
     uint32_t all;
-    const uint32_t base = lz_block_excl(t, lds4, &all) + tile_off[blockIdx.x];
+    const uint32_t base = lz_block_excl(t, lds4, &all) + tile_off[blockIdx.x] + group[blockIdx.x / kLzScanGroup];
     uint32_t f[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -570,8 +596,10 @@ bool lz_line(uint32_t ni, uint32_t nj, uint32_t nk)
 
 size_t lz_ws_bytes(uint32_t ni, uint32_t nj, uint32_t nk)
 {
-    if (lz_line(ni, nj, nk))
-        return kLzStatusBytes + (uint64_t(nk) + kLzTile - 1) / kLzTile * 4;
+    if (lz_line(ni, nj, nk)) {
+        const uint64_t nt = (uint64_t(nk) + kLzTile - 1) / kLzTile;
+        return kLzStatusBytes + nt * 4 + (nt + kLzScanGroup - 1) / kLzScanGroup * 4;
+    }
     const uint32_t r = lz_rows(ni, nj);
     const uint64_t nb = (uint64_t(nj) + r - 1) / r;
     return kLzStatusBytes + (nb > 1 ? size_t(ni) * nb * nk * 4 : 0);
@@ -652,12 +680,16 @@ extern "C" hd_status hd_lorenzo_reconstruct(const uint16_t *codes, uint32_t ni, 
         const uint32_t nt = static_cast<uint32_t>((uint64_t(nk) + kLzTile - 1) / kLzTile);
         const bool lvec = reinterpret_cast<uintptr_t>(codes) % 16 == 0;
         const bool ovec = reinterpret_cast<uintptr_t>(out) % 16 == 0 && reinterpret_cast<uintptr_t>(q_out) % 16 == 0;
+        const uint32_t ng = (nt + kLzScanGroup - 1) / kLzScanGroup;
+        uint32_t *groups = tiles + nt;
         hipLaunchKernelGGL(k_lz_line_sum, dim3(nt), dim3(kLzBlock), 0, stream, a, tiles, lvec);
-        hipLaunchKernelGGL(k_lz_line_scan, dim3(1), dim3(1024), 0, stream, tiles, nt);
+        hipLaunchKernelGGL(k_lz_line_scan, dim3(ng), dim3(kLzScanGroup), 0, stream, tiles, nt, groups);
+        hipLaunchKernelGGL(k_lz_line_top, dim3(1), dim3(kLzScanGroup), 0, stream, groups, ng);
         if (q_out)
-            hipLaunchKernelGGL(k_lz_line_out<true>, dim3(nt), dim3(kLzBlock), 0, stream, a, tiles, lvec, ovec);
+            hipLaunchKernelGGL(k_lz_line_out<true>, dim3(nt), dim3(kLzBlock), 0, stream, a, tiles, groups, lvec, ovec);
         else
-            hipLaunchKernelGGL(k_lz_line_out<false>, dim3(nt), dim3(kLzBlock), 0, stream, a, tiles, lvec, ovec);
+            hipLaunchKernelGGL(k_lz_line_out<false>, dim3(nt), dim3(kLzBlock), 0, stream, a, tiles, groups, lvec,
+                               ovec);
         return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
     }
     const bool vec = nk % 8 == 0 && reinterpret_cast<uintptr_t>(codes) % 16 == 0 &&

@@ -146,8 +146,9 @@ def test_reconstruction_workspace_sizes():
     assert hd.lorenzo_workspace_size((512, 512, 512)) == 256 + 512 * 16 * 512 * 4
     assert hd.lorenzo_workspace_size((64, 64, 64)) == 256 + 64 * 8 * 64 * 4          # R = 8
     assert hd.lorenzo_workspace_size((4, 8, 100)) == 256                              # one block: no table
-    # long 1-D fields: one uint32 per tile of 4096 values
-    assert hd.lorenzo_workspace_size((1, 1, 280_000_000)) == 256 + (280_000_000 + 4095) // 4096 * 4
+    # long 1-D fields: one uint32 per tile of 4096 values and per group of 1024 tiles
+    nt = (280_000_000 + 4095) // 4096
+    assert hd.lorenzo_workspace_size((1, 1, 280_000_000)) == 256 + nt * 4 + (nt + 1023) // 1024 * 4
     assert hd.lorenzo_workspace_size((1, 1, 4096)) == 256
     assert hd.lorenzo_workspace_size((0, 5, 5)) == 256
 

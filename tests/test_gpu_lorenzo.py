@@ -87,7 +87,7 @@ def test_generator_fields(shape):
     _check_field(_more_outliers(F, 0.02, sum(shape)), "mixed")
 
 
-@pytest.mark.parametrize("n", [4097, 8192, 100_003, (1 << 20) + 7])
+@pytest.mark.parametrize("n", [4097, 8192, 100_003, (1 << 20) + 7, 5_000_011])
 def test_long_1d_fields(n):
     # ni = nj = 1 beyond one wavefront's row: reduce-then-scan over tiles
     F = hdsynth.lorenzo_field((1, 1, n), seed=n % 97, n_waves=2, noise_sigma=1e-3, eb=1e-3, radius=512)
