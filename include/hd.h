@@ -331,7 +331,7 @@ hd_status hd_encode_write(const uint16_t *syms, uint64_t n, const uint8_t *lengt
 
 /*
  * SZ-style reconstruction of the field behind decoded quantization codes (the
- * step after Huffman decoding in the cuSZ decompression of Sec. V-C; the
+ * step after Huffman decoding in the cuSZ decompression of Sec. V-B-2; the
  * error-bounded scheme of Sec. II-A).  The codes are the first-order 3-D
  * Lorenzo prediction residuals of the prequantized integer field q, shifted
  * by radius, with code 0 marking a residual held in the outlier list:

@@ -5,7 +5,7 @@ CPU-baseline leg are the only callers.  The product library never imports or
 runs this file, and this file uses nothing from the product library.
 
 What is computed.  The decoded symbols are SZ quantization codes (Sec. II-A:
-error-bounded lossy compression; Sec. V-C evaluates the whole cuSZ
+error-bounded lossy compression; Sec. V-B-2 evaluates the whole cuSZ
 decompression around the decoder).  The paper states the pipeline only in
 outline; the reading taken here is the first-order Lorenzo scheme with
 prequantization that cuSZ uses:
@@ -21,7 +21,8 @@ prequantization that cuSZ uses:
 The predictor's inverse has a plain definition: q at (i, j, k) is the sum of
 the residuals over the box [0, i] x [0, j] x [0, k] (an inclusive prefix sum
 along every axis).  Integers are int64 here (exact); the dequantized value is
-the float64 product rounded once to float32.
+the product q * (2 eb) taken in float64 (one IEEE rounding) and then rounded to
+float32.
 """
 from __future__ import annotations
 
@@ -59,7 +60,7 @@ def inverse_lorenzo(r: np.ndarray, shape) -> np.ndarray:
 
 
 def dequantize(q: np.ndarray, eb: float) -> np.ndarray:
-    """value = q * (2 eb), product in float64, rounded once to float32."""
+    """value = q * (2 eb): the float64 product, then rounded to float32."""
     return (np.asarray(q, dtype=np.int64).astype(np.float64) * (2.0 * float(eb))).astype(np.float32)
 
 

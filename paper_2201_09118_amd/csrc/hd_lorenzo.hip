@@ -1,7 +1,7 @@
 // SZ-style reconstruction after Huffman decoding, for gfx950.
 //
 // The decoded symbols are quantization codes of a 3-D field (Sec. II-A:
-// error-bounded lossy compression; Sec. V-C measures the whole cuSZ
+// error-bounded lossy compression; Sec. V-B-2 measures the whole cuSZ
 // decompression around the decoder).  Each code is a first-order Lorenzo
 // prediction residual of the prequantized integer field q, shifted by a
 // radius, with code 0 marking a residual held in a separate outlier list
@@ -10,7 +10,7 @@
 //   r(i,j,k) = code - radius, or the listed residual where code == 0;
 //   q(i,j,k) = sum of r over the box [0,i] x [0,j] x [0,k]   (the inverse of
 //              the predictor: an inclusive prefix sum along every axis);
-//   x(i,j,k) = q * 2 eb, the float64 product rounded once to float32.
+//   x(i,j,k) = q * 2 eb, the float64 product converted to float32.
 //
 // Three kernels, all streaming HBM-bound work (no contraction, no MFMA):
 //

@@ -75,6 +75,58 @@ def test_generator_field_recovered_within_error_bound():
     assert (err <= F.eb * (1 + 1e-9) + 2 * slack).all()
 
 
+def _round_to_bits(x, p):
+    """The rational x rounded to p significant bits, ties to even (exact)."""
+    from fractions import Fraction
+    if x == 0:
+        return Fraction(0)
+    a = abs(x)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    while Fraction(2) ** e > a:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= a:
+        e += 1
+    scale = Fraction(2) ** (e - (p - 1))
+    m = a / scale
+    fl = m.numerator // m.denominator
+    rem = m - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return (fl * scale) if x > 0 else -(fl * scale)
+
+
+def _binary32_bits(x):
+    """IEEE binary32 bit pattern of a rational that is a normal float32."""
+    from fractions import Fraction
+    s = 1 if x < 0 else 0
+    a = abs(x)
+    e = 0
+    while Fraction(2) ** e > a:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= a:
+        e += 1
+    m = a / Fraction(2) ** (e - 23)
+    assert m.denominator == 1 and (1 << 23) <= m.numerator < (1 << 24)
+    return (s << 31) | ((e + 127) << 23) | (m.numerator - (1 << 23))
+
+
+def test_dequantize_golden_separates_double_from_float_product(golden):
+    """Pins the reading "q * 2eb in double, then rounded to float32" with
+    cases where a float32 product gives different bits
+    (tests/golden/dequantize_f64_product.txt, worked with exact rationals)."""
+    from fractions import Fraction
+    g = golden("dequantize_f64_product.txt")
+    assert len(g["case"]) >= 4
+    for eb_s, q_s, want_s, f32_s in g["case"]:
+        eb, q, want, f32_bits = float(eb_s), int(q_s), int(want_s), int(f32_s)
+        two_eb = Fraction(2.0 * eb)
+        exact = _binary32_bits(_round_to_bits(_round_to_bits(Fraction(q) * two_eb, 53), 24))
+        f32 = _binary32_bits(_round_to_bits(_round_to_bits(Fraction(q), 24) * _round_to_bits(two_eb, 24), 24))
+        assert exact == want and f32 == f32_bits and want != f32_bits
+        got = sz.dequantize(np.array([q], np.int64), eb).view(np.uint32)[0]
+        assert int(got) == want
+
+
 def test_dequantize_single_rounding():
     q = np.array([0, 1, -1, 3, 12345, -987654, (1 << 31) - 1], np.int64)
     eb = 1e-4
