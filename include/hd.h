@@ -20,9 +20,15 @@
  *                subsequence): gap[k] = p_k - k*S, p_k the first codeword
  *                start at or after bit k*S, the stream end counting as a
  *                start.  Always 0 <= gap[k] < max_len.
- *   chunk_counts uint32[n_chunks]: codewords whose FIRST bit lies in chunk c
- *                (subsequences [c*C, (c+1)*C)); their exclusive prefix sum is
- *                the first output index of each chunk (Sec. III-B, step 3).
+ *   chunk_offsets uint64[n_chunks + 1]: chunk_offsets[c] = the number of
+ *                codewords whose FIRST bit lies before chunk c (subsequences
+ *                [c*C, (c+1)*C)), i.e. the output index of the chunk's first
+ *                symbol; chunk_offsets[0] = 0, chunk_offsets[n_chunks] =
+ *                n_symbols.  These are the output indices of Sec. III-B,
+ *                step 3 at chunk granularity, stored by the encoder so that a
+ *                gap-array decode needs no device-wide scan (the paper's
+ *                decoder derives them by a redundant decoding pass and a
+ *                prefix sum, Sec. IV-C).
  *   S = subseq_bits (a multiple of 32), C = chunk_subseqs,
  *   n_subseq = ceil(n_bits / S), n_chunks = ceil(n_subseq / C).
  *
@@ -67,7 +73,7 @@ typedef enum {
 typedef enum {
     HD_MODE_GAP = 0,          /* start each subsequence from the gap array       */
     HD_MODE_SELF_SYNC = 1     /* find the starts by self-synchronization; reads
-                                 neither gap nor chunk_counts (may be NULL)      */
+                                 neither gap nor chunk_offsets (may be NULL)     */
 } hd_mode;
 
 typedef struct {
@@ -104,7 +110,7 @@ typedef struct {
 typedef struct {
     const uint32_t *words;
     const uint8_t *gap;            /* HD_MODE_GAP only */
-    const uint32_t *chunk_counts;  /* HD_MODE_GAP only */
+    const uint64_t *chunk_offsets; /* HD_MODE_GAP only */
     hd_stream_info info;
     const hd_table *table;
 } hd_dstream;
@@ -130,17 +136,29 @@ hd_status hd_build_codebook(const uint64_t *hist, uint32_t A, uint32_t L,
 
 /*
  * Reference encoder (host): packs syms[n] with the codebook into the stream
- * format above and emits the gap array (Sec. III-C) and per-chunk codeword
- * counts.  Two-call use: with words == NULL only *info is filled (sizes);
- * then call again with buffers of at least info->n_words / n_subseq /
- * n_chunks entries.  Returns HD_ERR_SYMBOL for a symbol >= A or without a
+ * format above and emits the gap array (Sec. III-C) and the chunk offsets.
+ * Two-call use: with words == NULL only *info is filled (sizes); then call
+ * again with buffers of at least info->n_words / n_subseq / n_chunks + 1
+ * entries.  Returns HD_ERR_SYMBOL for a symbol >= A or without a
  * codeword, HD_ERR_ARG for a bad layout (S not a positive multiple of 32,
  * C == 0) or short buffers.  The codebook need not be canonical.  Synchronous.
  */
 hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8_t *lengths,
                         const uint32_t *codes, uint32_t A, uint32_t L, const hd_layout *lay,
                         uint32_t *words, uint64_t words_cap, uint8_t *gap, uint64_t gap_cap,
-                        uint32_t *chunk_counts, uint64_t chunk_cap, hd_stream_info *info);
+                        uint64_t *chunk_offsets, uint64_t chunk_cap, hd_stream_info *info);
+
+/*
+ * The stream-format sizes of n_symbols symbols coded in n_bits bits under
+ * *lay, alphabet A and length limit L: fills *info (n_words = n_subseq * S /
+ * 32 + 2, n_subseq = ceil(n_bits / S), n_chunks = ceil(n_subseq / C); the
+ * chunk-offset array has n_chunks + 1 entries).  HD_ERR_ARG for a bad layout
+ * (S not a positive multiple of 32, C == 0), A outside [1, 65536] or L outside
+ * [1, 32]; HD_ERR_CORRUPT when n_bits is outside [n_symbols, n_symbols * L].
+ * Synchronous, host only.
+ */
+hd_status hd_stream_layout(uint64_t n_symbols, uint64_t n_bits, uint32_t A, uint32_t L, const hd_layout *lay,
+                           hd_stream_info *info);
 
 /* --------------------------------------------------------------- device -- */
 
@@ -167,11 +185,13 @@ size_t hd_table_lds_bytes(const hd_table *t);
 
 /*
  * Device workspace bytes hd_decode needs for stream s in mode m (tune may be
- * NULL).  The workspace holds the status word and the output-index scan
- * (self-sync mode also: the found sync points, per-tile totals and records,
- * and the list of tiles finished by the unconverged-tile pass); it needs no
- * initialization (every counter in it is cleared on the device, by a kernel,
- * at the start of each call).
+ * NULL).  The workspace holds the status area: a 256-byte header (word 0:
+ * status bits of the synchronization phase; word 1: the number of per-
+ * wavefront status slots the last decode kernel wrote) and the slots
+ * themselves.  In HD_MODE_SELF_SYNC it also holds the output-index scan of
+ * the per-tile totals, the found sync points, per-tile records and the
+ * pending-tile flags.  It needs no initialization: every word a call reads
+ * is written by that call's kernels first.
  */
 hd_status hd_decode_workspace_size(const hd_dstream *s, hd_mode m, const hd_tune *tune,
                                    size_t *bytes);
@@ -179,15 +199,15 @@ hd_status hd_decode_workspace_size(const hd_dstream *s, hd_mode m, const hd_tune
 /*
  * Decodes one stream into out[0 .. n_symbols) (device memory).
  * HD_MODE_GAP: each subsequence starts at k*S + gap[k] (Sec. III-C); output
- * indices are the exclusive prefix sum of chunk_counts, refined per
- * subsequence by a wavefront scan of decoded counts (Sec. III-B, step 3);
- * symbols are staged in LDS and written with coalesced stores (Sec. IV-B,
- * Algorithm 1).
+ * indices are the stored chunk offsets, refined per subsequence by a
+ * wavefront scan of decoded counts (Sec. III-B, step 3); symbols are staged
+ * in LDS and written with coalesced stores (Sec. IV-B, Algorithm 1).  One
+ * kernel launch.
  * HD_MODE_SELF_SYNC: the sync point of every subsequence is found by
  * decoding from the raw boundary until the path meets the previous
  * subsequence's verified exit (Sec. III-B-2, steps 1-2), the counts found on
  * the way are scanned (step 3) and the decode/write step is the same as in
- * gap mode (step 4).  No gap or chunk_counts input is read.
+ * gap mode (step 4).  No gap or chunk_offsets input is read.
  * Asynchronous on hip_stream.  Returns HD_ERR_ARG / HD_ERR_UNSUPPORTED for
  * bad arguments (including a workspace smaller than
  * hd_decode_workspace_size), HD_ERR_DEVICE for launch failures.  Faults in
@@ -199,8 +219,8 @@ hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune
 /*
  * hd_decode in two parts, for callers that time the phases or decode one
  * stream repeatedly.  hd_decode_prepare enqueues the output-index phase
- * (gap mode: the chunk-offset scan of chunk_counts; self-sync mode: the
- * synchronization steps 1-3 of Sec. III-B-2) and leaves its result in the
+ * (gap mode: nothing, the offsets are stored in the stream; self-sync mode:
+ * the synchronization steps 1-3 of Sec. III-B-2) and leaves its result in the
  * workspace; hd_decode_run enqueues the decode-and-write step (step 4,
  * Sec. IV-B) reading that result.  prepare followed by run on one stream
  * equals hd_decode; run may be repeated while the workspace is untouched.
@@ -232,8 +252,7 @@ hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, uint32_t n_s
 /*
  * Decodes n_streams independent streams, each with its own table, layout and
  * alphabet, into outs[i] (device memory, n_symbols of stream i, 16-byte
- * aligned) with one segmented chunk-offset scan and one persistent decode
- * launch.  The paper groups sequences by compression ratio and launches one
+ * aligned) with one persistent decode launch.  The paper groups sequences by compression ratio and launches one
  * kernel per group, each with its own shared-memory size (Sec. IV-C, Alg. 2);
  * here workgroups walk (stream, group of tiles) items of every stream and
  * reload the LDS decode table only when the stream changes.  The launch's LDS
@@ -270,11 +289,12 @@ hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *out, void *
                       size_t ws_bytes, void *hip_stream, hd_tune *best, float *best_ms);
 
 /*
- * Waits for hip_stream, then reads the status word the last decode on this
- * workspace left: HD_OK, or HD_ERR_CORRUPT when a lane met an invalid
- * codeword, a subsequence ended off its successor's start, a chunk's decoded
- * count differed from chunk_counts, the counts did not add up to n_symbols,
- * or self-synchronization found no consistent sync point.
+ * Waits for hip_stream, then reads the status the last decode on this
+ * workspace left (the header word and every slot the decode kernel wrote):
+ * HD_OK, or HD_ERR_CORRUPT when a lane met an invalid codeword, a
+ * subsequence ended off its successor's start, a chunk's decoded count
+ * differed from its chunk offsets, the offsets did not start at 0 and end at
+ * n_symbols, or self-synchronization found no consistent sync point.
  */
 hd_status hd_decode_status(const void *workspace, void *hip_stream);
 
@@ -282,10 +302,13 @@ hd_status hd_decode_status(const void *workspace, void *hip_stream);
  * The raw status bits behind hd_decode_status (0 = clean; 0xffffffff when the
  * word could not be read).  Bit 0: a gap byte beyond any codeword length;
  * 1: a window matching no codeword; 2: a subsequence ending off its
- * successor's start; 3: a chunk count mismatch; 4: counts not adding up to
- * n_symbols; 5: an output index outside [0, n_symbols); 6: no consistent
- * self-synchronization point; 7: a code-0 position missing from the outlier
- * list (hd_lorenzo_reconstruct).  Waits for hip_stream first.
+ * successor's start; 3: a chunk's decoded count differing from its offsets;
+ * 4: chunk offsets not starting at 0 or not ending at n_symbols (self-sync:
+ * found counts not adding up to n_symbols); 5: an output index outside
+ * [0, n_symbols); 6: self-synchronization found no consistent sync point
+ * (the synchronized path from bit 0 does not end on bit n_bits); 7: a code-0
+ * position missing from the outlier list (hd_lorenzo_reconstruct).  Waits
+ * for hip_stream first.
  */
 uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream);
 
@@ -293,7 +316,7 @@ uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream);
 
 /*
  * Device-side encoding into the stream format above: the same words, gap
- * array (Sec. III-C) and chunk counts as hd_encode_ref, bit for bit.  All
+ * array (Sec. III-C) and chunk offsets as hd_encode_ref, bit for bit.  All
  * buffers are device memory owned by the caller; calls are asynchronous on
  * hip_stream except hd_encode_bits.
  *
@@ -310,7 +333,7 @@ uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream);
  *   ceil(n_subseq / C), n_words = n_subseq * S / 32 + 2.
  * hd_encode_write: packs syms[n] with lengths[A] / codes[A] (device, codes
  *   right-aligned) into words[n_words] (zero-filled by the call, guard units
- *   included), gap[n_subseq] and chunk_counts[n_chunks].  Needs the plan of
+ *   included), gap[n_subseq] and chunk_offsets[n_chunks + 1].  Needs the plan of
  *   the same symbols in the same workspace.  HD_ERR_ARG for a bad layout,
  *   n_chunks != ceil(n_subseq / C), a workspace below
  *   hd_encode_workspace_size or NULL buffers.  A unit index beyond n_words
@@ -324,7 +347,7 @@ hd_status hd_encode_plan(const uint16_t *syms, uint64_t n, const uint8_t *length
 hd_status hd_encode_bits(const void *workspace, uint64_t *n_bits, void *hip_stream);
 hd_status hd_encode_write(const uint16_t *syms, uint64_t n, const uint8_t *lengths, const uint32_t *codes,
                           uint32_t A, const hd_layout *lay, uint32_t *words, uint64_t n_words, uint8_t *gap,
-                          uint64_t n_subseq, uint32_t *chunk_counts, uint64_t n_chunks, void *workspace,
+                          uint64_t n_subseq, uint64_t *chunk_offsets, uint64_t n_chunks, void *workspace,
                           size_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------ reconstruction -- */

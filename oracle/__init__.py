@@ -116,6 +116,14 @@ class Encoded:
     def n_chunks(self):
         return self.chunk_counts.size
 
+    @property
+    def chunk_offsets(self) -> np.ndarray:
+        """uint64[M + 1]: the output index of each chunk's first codeword (the
+        exclusive prefix sum of the chunk counts, Sec. III-B step 3), then n."""
+        off = np.zeros(self.chunk_counts.size + 1, dtype=np.uint64)
+        np.cumsum(self.chunk_counts, dtype=np.uint64, out=off[1:])
+        return off
+
 
 def encode(x: np.ndarray, lengths: np.ndarray, codes: np.ndarray, S: int = 128, C: int = 32) -> Encoded:
     x = np.ascontiguousarray(x, dtype=np.uint16)
@@ -172,17 +180,18 @@ def decode_from(words, n_bits, start, n, lengths, codes, out=None):
     return out, int(end[0])
 
 
-def decode_chunks_parallel(words, n_bits, n, lengths, codes, gap, chunk_counts, S, C, threads):
+def decode_chunks_parallel(words, n_bits, n, lengths, codes, gap, chunk_offsets, S, C, threads):
     """The bit-serial decoder run on `threads` host threads, one contiguous
     range of chunks each, every range starting at its first subsequence's gap
-    entry.  Returns the decoded symbols."""
+    entry and writing from its first chunk's offset (chunk_offsets: uint64[M + 1]).
+    Returns the decoded symbols."""
     from concurrent.futures import ThreadPoolExecutor
     words = np.ascontiguousarray(words, dtype=np.uint32)
     lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
     codes = np.ascontiguousarray(codes, dtype=np.uint32)
     out = np.zeros(n, dtype=np.uint16)
-    M = int(chunk_counts.size)
-    off = np.concatenate([[0], np.cumsum(chunk_counts.astype(np.uint64))]).astype(np.uint64)
+    M = int(chunk_offsets.size) - 1
+    off = np.ascontiguousarray(chunk_offsets, dtype=np.uint64)
     bounds = [M * i // threads for i in range(threads + 1)]
 
     def run(i):

@@ -1,13 +1,14 @@
 // Device half of the library: decode tables, output-index scans and the
 // decode kernels for AMD Instinct MI355X (gfx950, wave64, 160 KiB LDS/CU).
 //
-// Hot path (gap mode), per wavefront of 64 lanes, one lane per subsequence:
+// Hot path (gap mode): one kernel launch; per wavefront of 64 lanes, one lane
+// per subsequence:
 //   1. copy the tile's 32-bit units into LDS with coalesced loads;
 //   2. start at k*S + gap[k] (Sec. III-C) and count the codewords that start
 //      inside the subsequence (the paper's "redundant decoding" to learn
-//      where each thread writes, Sec. IV-C; the chunk totals come from the
-//      stream's chunk_counts, so this pass only spans one subsequence),
-//      keeping the table entries it reads in registers (pair format);
+//      where each thread writes, Sec. IV-C; the chunk offsets are stored in
+//      the stream, so this pass only spans one subsequence), keeping the
+//      table entries it reads in registers (pair format);
 //   3. wavefront exclusive scan of the counts gives each lane its output
 //      index inside the tile (Sec. III-B, step 3);
 //   4. write the symbols into an LDS staging tile (Sec. IV-B, Algorithm 1)
@@ -681,12 +682,9 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh)
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__restrict__ cc,
-                                                              uint64_t M, uint64_t *partial,
-                                                              uint32_t *status)
+                                                              uint64_t M, uint64_t *partial)
 {
     __shared__ uint64_t sh[kScanThreads / 64];
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        *status = 0;
     const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * kScanBlock;
     uint64_t s = 0;
     for (int i = 0; i < kScanPerThread; ++i) {
@@ -774,11 +772,26 @@ inline uint32_t chunk_log2(uint32_t C)
     return l;
 }
 
+// Status of a decode launch: the workspace header (word 0: status bits of
+// the phases before the decode kernel; word 1: the number of slots) and one
+// slot per wavefront, each written once per launch (no clearing needed, so a
+// gap-mode decode is a single launch).
 struct GapArgs {
     StreamDev sd;
-    uint32_t *status;
+    uint32_t *head;
+    uint32_t *slots;
+    uint32_t own_head;           // gap mode: the kernel also writes head[0] and checks the offsets
     TableView tab;
 };
+
+// OR of err over the wavefront's lanes (every lane active).
+__device__ __forceinline__ uint32_t wave_or(uint32_t e)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1)
+        e |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(e), d, kWave));
+    return e;
+}
 
 // LDS of one wave's private area: the transposed unit copy TT (S/32 + 2
 // words per lane, 64 lanes), the staging tile, and 64 dummy uint16 slots
@@ -1080,6 +1093,9 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
     const uint64_t ntiles = (sd.K + 63) >> 6;
     const uint32_t wpg = blockDim.x >> 6;
     const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * wpg;
+    // stored chunk offsets must start at 0 and end at n
+    if (a.own_head && blockIdx.x == 0 && threadIdx.x == 0 && (sd.chunk_off[0] != 0 || sd.chunk_off[sd.M] != sd.n))
+        err |= kErrTotal;
     // Tile inputs travel through registers one tile ahead: while tile t is
     // decoded, the inputs of the wavefront's next tile are in flight.
     TileInT<MAXU> in;
@@ -1095,8 +1111,14 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
         decode_tile<PAIR, PAIR ? kLogIters : 0>(sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, g, sh,
                                                 err);
     }
-    if (err)
-        atomicOr(a.status, err);
+    err = wave_or(err);
+    if (lane == 0)
+        a.slots[blockIdx.x * wpg + wv] = err;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.head[1] = gridDim.x * wpg;
+        if (a.own_head)
+            a.head[0] = 0;
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -1149,7 +1171,7 @@ struct SyncArgs {
     uint8_t *gap_s;           // [K] sync point of every subsequence (relative)
     uint32_t *tot;            // [ntiles] codewords per tile
     SyncRec *rec;             // [ntiles]
-    uint32_t *status;
+    uint32_t *status;         // the workspace header word 0 (cleared with n_pending)
     uint32_t *n_pending;      // tiles step 1 left unconverged (zero at launch)
     uint32_t *pending;        // [ntiles] their indices
     TableView tab;
@@ -1274,6 +1296,9 @@ __device__ uint32_t sync_and_store(const SyncArgs &a, uint64_t t, uint32_t *TTl,
     const uint32_t E = lane_end(k, a.K, a.B, S);
     uint32_t start, exit, cnt;
     const bool done = sync_tile<PAIR>(TTl, lane, act, E, S, e0, max_rounds, st, g, sh, start, exit, cnt);
+    // the stream's last subsequence must end exactly on the stream end (a
+    // codeword path that runs past it found no consistent sync point)
+    const bool off_end = k + 1 == a.K && exit != E;
     // only the round-limited pass lists tiles (each at most once, so the
     // list index stays below ntiles); kMaxRounds always converges
     if (!done && max_rounds < kMaxRounds && lane == 0)
@@ -1305,6 +1330,10 @@ __device__ uint32_t sync_and_store(const SyncArgs &a, uint64_t t, uint32_t *TTl,
             run_path<PAIR>(TT0, lane, E0, st, g, sh, exg, cng);
         const bool differs = probe && exg != ex0;
         const bool indep = __builtin_amdgcn_ballot_w64(differs) == 0;
+        // the tile's paths are final when its entry is (tile 0) or does not
+        // matter, and the rounds converged; otherwise a later kernel decides
+        if (off_end && done && (t == 0 || indep))
+            atomicOr(a.status, kErrNoSync);
         SyncRec *r = a.rec + t;
         if (lane < 32)
             r->count_at[lane] = static_cast<uint16_t>(probe ? cng : 0u);
@@ -1313,9 +1342,14 @@ __device__ uint32_t sync_and_store(const SyncArgs &a, uint64_t t, uint32_t *TTl,
             r->indep = indep ? 1 : 0;
             a.tot[t] = total;
         }
-    } else if (lane == 0) {
-        a.tot[t] = total;
-        a.rec[t].last_entry = static_cast<uint8_t>(last_exit - S);
+    } else {
+        // re-synced from the true entry with enough rounds: final
+        if (off_end)
+            atomicOr(a.status, kErrNoSync);
+        if (lane == 0) {
+            a.tot[t] = total;
+            a.rec[t].last_entry = static_cast<uint8_t>(last_exit - S);
+        }
     }
     return last_exit - S;
 }
@@ -1327,8 +1361,6 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_sync(SyncArgs a)
     const TableView &g = a.tab;
     const SmemTable st = carve_table(smem, g.k1);
     load_table(st, g);
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        *a.status = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wv = wave_index();
@@ -1396,6 +1428,11 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
             }
             ent[0] = 0;
             a.rec[t].last_entry = static_cast<uint8_t>(e);
+            // the stream's last tile, final when its entry is (tile 0) or
+            // does not matter: its last path must end on the stream end
+            // (e is that lane's exit minus its end)
+            if ((t + 1) << 6 >= a.K && (t == 0 || a.rec[t].indep) && e != 0)
+                atomicOr(a.status, kErrNoSync);
         }
         __syncthreads();
         if (wv == 0) {
@@ -1416,10 +1453,15 @@ __host__ __device__ __forceinline__ uint32_t pending_lds_bytes(uint32_t k1, uint
     return table_lds_bytes(k1) + wave_units_bytes(S) + 64 * 32 * 3 + 64;
 }
 
-__global__ void k_zero_u32(uint32_t *p)
+// Clears the pending-tile count and the status header word before the
+// synchronization kernels run (a kernel, not a memset, so the sequence can be
+// captured in a graph).
+__global__ void k_ss_clear(uint32_t *n_pending, uint32_t *status)
 {
-    if (threadIdx.x == 0)
-        *p = 0;
+    if (threadIdx.x == 0) {
+        *n_pending = 0;
+        *status = 0;
+    }
 }
 
 template <int WPG, bool PAIR>
@@ -1474,8 +1516,9 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
 // item belongs to another stream: only then do the waves meet at a barrier
 // while the stream's table is loaded into LDS.  Otherwise waves run on their
 // own, with the next item's tile inputs in registers while the current tile
-// decodes, as in the single-stream kernel.  Per-stream chunk offsets come
-// from one segmented scan over the batch.
+// decodes, as in the single-stream kernel.  Chunk offsets are the streams'
+// own (stored by the encoder); the status word comes zeroed with the
+// uploaded descriptors.
 
 struct BatchStreamDev {
     StreamDev sd;
@@ -1548,6 +1591,10 @@ __global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
             in.load(nb.sd, (nitem - nb.item0) * wpg + wv, nb.ntiles, lane);
         }
         wave_lds_sync();
+        // a stream's stored offsets must start at 0 and end at its n
+        if (live && t == 0 && lane == 0 &&
+            (bs.sd.chunk_off[0] != 0 || bs.sd.chunk_off[bs.sd.M] != bs.sd.n))
+            err |= kErrTotal;
         if (live) {
             const SmemTable st = carve_table(smem, bs.tab.k1);
             const uint32_t sh = 32 - bs.tab.k1;
@@ -1563,78 +1610,6 @@ __global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
         atomicOr(a.status, err);
 }
 
-// Segmented scan of every stream's chunk counts.
-struct BatchScanStream {
-    const uint32_t *cc;
-    uint64_t *off;            // [M + 1]
-    uint64_t M, n;
-    uint32_t blk0, nblk;      // the stream's blocks in the global block list
-};
-
-struct BatchScanBlock {
-    uint32_t stream, blk;
-};
-
-__global__ __launch_bounds__(kScanThreads) void k_bscan_reduce(const BatchScanStream *ss, const BatchScanBlock *bl,
-                                                               uint64_t *partial, uint32_t *status)
-{
-    __shared__ uint64_t sh[kScanThreads / 64];
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        *status = 0;
-    const BatchScanBlock b = bl[blockIdx.x];
-    const BatchScanStream st = ss[b.stream];
-    const uint64_t b0 = static_cast<uint64_t>(b.blk) * kScanBlock;
-    uint64_t s = 0;
-    for (int i = 0; i < kScanPerThread; ++i) {
-        const uint64_t c = b0 + static_cast<uint64_t>(i) * kScanThreads + threadIdx.x;
-        if (c < st.M)
-            s += st.cc[c];
-    }
-    s = block_sum_u64(s, sh);
-    if (threadIdx.x == 0)
-        partial[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_bscan_finish(const BatchScanStream *ss, const BatchScanBlock *bl,
-                                                               const uint64_t *partial, uint32_t *status)
-{
-    __shared__ uint64_t sh[kScanThreads / 64];
-    __shared__ uint64_t tsum[kScanThreads];
-    const BatchScanBlock b = bl[blockIdx.x];
-    const BatchScanStream st = ss[b.stream];
-    uint64_t pre = 0;
-    for (uint32_t i = threadIdx.x; i < b.blk; i += blockDim.x)
-        pre += partial[st.blk0 + i];
-    pre = block_sum_u64(pre, sh);
-    const uint64_t my0 = static_cast<uint64_t>(b.blk) * kScanBlock + static_cast<uint64_t>(threadIdx.x) * kScanPerThread;
-    uint32_t v[kScanPerThread];
-    uint64_t s = 0;
-    for (int i = 0; i < kScanPerThread; ++i) {
-        v[i] = (my0 + i < st.M) ? st.cc[my0 + i] : 0u;
-        s += v[i];
-    }
-    tsum[threadIdx.x] = s;
-    __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {
-        const uint64_t o = threadIdx.x >= (unsigned)d ? tsum[threadIdx.x - d] : 0;
-        __syncthreads();
-        tsum[threadIdx.x] += o;
-        __syncthreads();
-    }
-    uint64_t run = pre + tsum[threadIdx.x] - s;
-    for (int i = 0; i < kScanPerThread; ++i) {
-        if (my0 + i < st.M)
-            st.off[my0 + i] = run;
-        run += v[i];
-    }
-    if (b.blk == st.nblk - 1 && threadIdx.x == kScanThreads - 1) {
-        const uint64_t total = pre + tsum[kScanThreads - 1];
-        st.off[st.M] = total;
-        if (total != st.n)
-            atomicOr(status, kErrTotal);
-    }
-}
-
 }  // namespace
 
 // ------------------------------------------------------------------------
@@ -1643,7 +1618,11 @@ __global__ __launch_bounds__(kScanThreads) void k_bscan_finish(const BatchScanSt
 
 namespace {
 
-constexpr size_t kWsHeader = 256;          // status word + padding
+constexpr size_t kWsHeader = 256;          // status header: word 0 status bits, word 1 slot count
+// Status slots after the header: one per resident wavefront of a decode
+// launch (the plan keeps grid x waves per workgroup within this).
+constexpr uint32_t kMaxSlots = 8192;
+constexpr size_t kWsStatusBytes = kWsHeader + 4 * size_t(kMaxSlots);
 
 constexpr uint32_t kMaxWavesPerGroup = 16;    // 1024 work-items
 constexpr uint32_t kMaxWavesPerCu = 32;       // 8 wavefronts per SIMD
@@ -1752,7 +1731,7 @@ hd_status check_stream(const hd_dstream *s, hd_mode m)
     if (m == HD_MODE_GAP) {
         if (64 % i.chunk_subseqs != 0)
             return HD_ERR_UNSUPPORTED;
-        if (K && (!s->gap || !s->chunk_counts))
+        if ((K && !s->gap) || !s->chunk_offsets)
             return HD_ERR_ARG;
     } else if (m != HD_MODE_SELF_SYNC) {
         return HD_ERR_ARG;
@@ -1886,15 +1865,20 @@ hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
     p->groups_per_cu = tune && tune->groups_per_cu ? std::min(tune->groups_per_cu, fit) : fit;
     const uint64_t ntiles = ceil_div(s->info.n_subseq, 64);
     const uint64_t want = ceil_div(ntiles, p->wpg);
-    const uint64_t cap = uint64_t(dev->cus) * p->groups_per_cu;
+    const uint64_t cap = std::min<uint64_t>(uint64_t(dev->cus) * p->groups_per_cu, kMaxSlots / p->wpg);
     p->grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min(want, cap)));
     return HD_OK;
 }
 
-size_t gap_ws_bytes(uint64_t M)
+// Gap mode: the status area only (the chunk offsets are the stream's).
+size_t gap_ws_bytes() { return kWsStatusBytes; }
+
+// The status area plus an output-index scan over M chunks: offsets [M + 1]
+// and the scan's block partials.
+size_t scan_ws_bytes(uint64_t M)
 {
     const uint64_t nblk = std::max<uint64_t>(1, ceil_div(M, kScanBlock));
-    return kWsHeader + align_up(8 * (M + 1), 256) + align_up(8 * nblk, 256);
+    return kWsStatusBytes + align_up(8 * (M + 1), 256) + align_up(8 * nblk, 256);
 }
 
 // Self-sync workspace: the gap-mode part sized for one chunk per tile, then
@@ -1910,14 +1894,14 @@ struct SyncWs {
 size_t sync_ws_bytes(uint64_t K)
 {
     const uint64_t nt = ceil_div(K, 64);
-    return gap_ws_bytes(nt) + align_up(K, 256) + 2 * align_up(4 * nt, 256) + align_up(kSyncRecBytes * nt, 256) +
+    return scan_ws_bytes(nt) + align_up(K, 256) + 2 * align_up(4 * nt, 256) + align_up(kSyncRecBytes * nt, 256) +
            256;
 }
 
 SyncWs sync_ws(void *workspace, uint64_t K)
 {
     const uint64_t nt = ceil_div(K, 64);
-    char *p = static_cast<char *>(workspace) + gap_ws_bytes(nt);
+    char *p = static_cast<char *>(workspace) + scan_ws_bytes(nt);
     SyncWs w;
     w.gap_s = reinterpret_cast<uint8_t *>(p);
     p += align_up(K, 256);
@@ -1946,9 +1930,6 @@ hd_status launch_sync(const SyncArgs &a, uint32_t grid, uint32_t lds, hipStream_
             return HD_ERR_DEVICE;
         attr_set = true;
     }
-    // the pending count is cleared by a kernel (not a memset) so the
-    // sequence can be captured in a graph
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, a.n_pending);
     hipLaunchKernelGGL((k_ss_sync<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
     hipLaunchKernelGGL((k_ss_pending<WPG, PAIR>), dim3(grid), dim3(WPG * 64),
                        pending_lds_bytes(a.tab.k1, a.S), stream, a);
@@ -2000,15 +1981,14 @@ hd_status launch_gap(const GapArgs &a, const Plan &p, hipStream_t stream)
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
 
-// Enqueues the chunk-offset scan: off[0..M] from chunk_counts.
+// Enqueues the scan of per-tile totals (self-sync mode): off[0..M].
 hd_status enqueue_chunk_scan(const uint32_t *cc, uint64_t M, uint64_t n, uint64_t *off,
                              uint64_t *partial, uint32_t *status, hipStream_t stream)
 {
     const uint64_t nblk = std::max<uint64_t>(1, ceil_div(M, kScanBlock));
     if (nblk > 0x7fffffffu)
         return HD_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kScanThreads), 0, stream, cc, M, partial,
-                       status);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kScanThreads), 0, stream, cc, M, partial);
     hipLaunchKernelGGL(k_scan_finish, dim3(nblk), dim3(kScanThreads), 0, stream, cc, M, partial,
                        off, n, status);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
@@ -2025,16 +2005,17 @@ extern "C" hd_status hd_decode_workspace_size(const hd_dstream *s, hd_mode m, co
     hd_status st = check_stream(s, m);
     if (st != HD_OK)
         return st;
-    *bytes = m == HD_MODE_GAP ? gap_ws_bytes(s->info.n_chunks) : sync_ws_bytes(s->info.n_subseq);
+    *bytes = m == HD_MODE_GAP ? gap_ws_bytes() : sync_ws_bytes(s->info.n_subseq);
     return HD_OK;
 }
 
 namespace {
 
 struct WsView {
-    uint32_t *status;
-    uint64_t *off;       // [M + 1] output index of each chunk
-    uint64_t *partial;   // scan partials
+    uint32_t *status;    // header word 0
+    uint32_t *slots;     // [kMaxSlots]
+    uint64_t *off;       // [M + 1] output index of each tile (self-sync mode)
+    uint64_t *partial;   // scan partials (self-sync mode)
 };
 
 WsView ws_view(void *workspace, uint64_t M)
@@ -2042,8 +2023,9 @@ WsView ws_view(void *workspace, uint64_t M)
     char *ws = static_cast<char *>(workspace);
     WsView v;
     v.status = reinterpret_cast<uint32_t *>(ws);
-    v.off = reinterpret_cast<uint64_t *>(ws + kWsHeader);
-    v.partial = reinterpret_cast<uint64_t *>(ws + kWsHeader + align_up(8 * (M + 1), 256));
+    v.slots = reinterpret_cast<uint32_t *>(ws + kWsHeader);
+    v.off = reinterpret_cast<uint64_t *>(ws + kWsStatusBytes);
+    v.partial = reinterpret_cast<uint64_t *>(ws + kWsStatusBytes + align_up(8 * (M + 1), 256));
     return v;
 }
 
@@ -2073,16 +2055,16 @@ extern "C" hd_status hd_decode_prepare(const hd_dstream *s, hd_mode m, const hd_
         return st;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const hd_stream_info &i = s->info;
-    if (m == HD_MODE_GAP) {
-        const WsView w = ws_view(workspace, i.n_chunks);
-        return enqueue_chunk_scan(s->chunk_counts, i.n_chunks, i.n_symbols, w.off, w.partial, w.status,
-                                  stream);
-    }
+    if (m == HD_MODE_GAP)
+        return HD_OK;          // the output indices are the stream's stored chunk offsets
     // self-sync: steps 1-2 find the sync points and tile totals, step 3 scans
     // the totals (one chunk per tile)
     const uint64_t nt = ceil_div(i.n_subseq, 64);
     const WsView w = ws_view(workspace, nt);
     const SyncWs sw = sync_ws(workspace, i.n_subseq);
+    // the status word is cleared once, here, before any kernel of the call
+    // can report into it
+    hipLaunchKernelGGL(k_ss_clear, dim3(1), dim3(64), 0, stream, sw.n_pending, w.status);
     if (i.n_subseq) {
         st = enqueue_sync(s, sw, w.status, stream);
         if (st != HD_OK)
@@ -2100,11 +2082,10 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     if ((s->info.n_symbols && !out) || reinterpret_cast<uintptr_t>(out) % 16 != 0)
         return HD_ERR_ARG;
     const hd_stream_info &i = s->info;
-    if (i.n_subseq == 0)
-        return HD_OK;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const bool ss = m == HD_MODE_SELF_SYNC;
     const uint64_t M = ss ? ceil_div(i.n_subseq, 64) : i.n_chunks;
+    // (an empty stream still launches the kernel: it writes the status)
     const WsView w = ws_view(workspace, M);
     Plan p;
     st = make_plan(s, tune, &p);
@@ -2113,7 +2094,7 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     GapArgs a;
     a.sd.words = s->words;
     a.sd.gap = ss ? sync_ws(workspace, i.n_subseq).gap_s : s->gap;
-    a.sd.chunk_off = w.off;
+    a.sd.chunk_off = ss ? w.off : s->chunk_offsets;
     a.sd.out = out;
     a.sd.n = i.n_symbols;
     a.sd.B = i.n_bits;
@@ -2124,7 +2105,9 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     a.sd.last_bits = i.n_subseq ? static_cast<uint32_t>(i.n_bits - (i.n_subseq - 1) * i.subseq_bits) : 0u;
     a.sd.Cl = ss ? 6u : chunk_log2(i.chunk_subseqs);
     a.sd.stage = p.stage;
-    a.status = w.status;
+    a.head = w.status;
+    a.slots = w.slots;
+    a.own_head = ss ? 0u : 1u;
     a.tab = view_of(s->table);
     const bool small = i.subseq_bits <= 32 * kSmallUnits;
     if (s->table->pair)
@@ -2165,39 +2148,17 @@ extern "C" hd_status hd_decode_sync_points(const hd_dstream *s, const void *work
 
 namespace {
 
-// Workspace layout of a batch: header (status word), stream
-// descriptors, scan descriptors, scan block list, scan partials, then every
-// stream's chunk offsets.
+// Workspace layout of a batch: the status header, then the stream
+// descriptors.  Both travel in one upload, so the status word starts zeroed
+// (word 1, the slot count, is 0: the batch kernel ORs into word 0).
 struct BatchLayout {
-    size_t desc, sdesc, blocks, partial, offs, total;
-    std::vector<size_t> off_at;   // byte offset of each stream's chunk offsets
-    uint32_t nblk_total;
+    size_t desc, total;
 };
 
-hd_status batch_layout(const hd_dstream *streams, uint32_t n, BatchLayout *L)
+hd_status batch_layout(uint32_t n, BatchLayout *L)
 {
-    size_t p = kWsHeader;
-    L->desc = p;
-    p += align_up(sizeof(BatchStreamDev) * n, 256);
-    L->sdesc = p;
-    p += align_up(sizeof(BatchScanStream) * n, 256);
-    uint64_t nb = 0;
-    for (uint32_t i = 0; i < n; ++i)
-        nb += std::max<uint64_t>(1, ceil_div(streams[i].info.n_chunks, kScanBlock));
-    if (nb > 0x7fffffffu)
-        return HD_ERR_UNSUPPORTED;
-    L->nblk_total = static_cast<uint32_t>(nb);
-    L->blocks = p;
-    p += align_up(sizeof(BatchScanBlock) * nb, 256);
-    L->partial = p;
-    p += align_up(8 * nb, 256);
-    L->offs = p;
-    L->off_at.resize(n);
-    for (uint32_t i = 0; i < n; ++i) {
-        L->off_at[i] = p;
-        p += align_up(8 * (streams[i].info.n_chunks + 1), 256);
-    }
-    L->total = p;
+    L->desc = kWsHeader;
+    L->total = kWsHeader + align_up(sizeof(BatchStreamDev) * size_t(n), 256);
     return HD_OK;
 }
 
@@ -2298,7 +2259,7 @@ extern "C" hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, u
             return st;
     }
     BatchLayout L;
-    hd_status st = batch_layout(streams, n_streams, &L);
+    hd_status st = batch_layout(n_streams, &L);
     if (st != HD_OK)
         return st;
     *bytes = L.total;
@@ -2323,7 +2284,7 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
     if (!dev)
         return HD_ERR_DEVICE;
     BatchLayout L;
-    st = batch_layout(streams, n_streams, &L);
+    st = batch_layout(n_streams, &L);
     if (st != HD_OK)
         return st;
     char *ws = static_cast<char *>(workspace);
@@ -2407,9 +2368,6 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
         fit = std::min(fit, t0->groups_per_cu);
 
     std::vector<BatchStreamDev> d(n_streams);
-    std::vector<BatchScanStream> ss(n_streams);
-    std::vector<BatchScanBlock> bl;
-    bl.reserve(L.nblk_total);
     uint64_t items = 0;
     for (uint32_t i = 0; i < n_streams; ++i) {
         const hd_dstream &s = streams[i];
@@ -2417,7 +2375,7 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
         BatchStreamDev &b = d[i];
         b.sd.words = s.words;
         b.sd.gap = s.gap;
-        b.sd.chunk_off = reinterpret_cast<const uint64_t *>(ws + L.off_at[i]);
+        b.sd.chunk_off = s.chunk_offsets;
         b.sd.out = outs[i];
         b.sd.n = si.n_symbols;
         b.sd.B = si.n_bits;
@@ -2434,41 +2392,24 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
         b.ntiles = ceil_div(si.n_subseq, 64);
         b.item0 = items;
         items += ceil_div(b.ntiles, wpg);
-        BatchScanStream &c = ss[i];
-        c.cc = s.chunk_counts;
-        c.off = reinterpret_cast<uint64_t *>(ws + L.off_at[i]);
-        c.M = si.n_chunks;
-        c.n = si.n_symbols;
-        c.blk0 = static_cast<uint32_t>(bl.size());
-        c.nblk = static_cast<uint32_t>(std::max<uint64_t>(1, ceil_div(si.n_chunks, kScanBlock)));
-        for (uint32_t k = 0; k < c.nblk; ++k)
-            bl.push_back({i, k});
     }
 
-    // upload descriptors through pinned staging
-    const size_t up = L.offs - L.desc;
+    // upload the zeroed status header and the descriptors through pinned
+    // staging, in one copy
+    const size_t up = L.total;
     StagingBuf *sb = staging_acquire(up);
     if (!sb)
         return HD_ERR_NOMEM;
     char *h = static_cast<char *>(sb->host);
     std::memset(h, 0, up);
-    std::memcpy(h + (L.desc - L.desc), d.data(), sizeof(BatchStreamDev) * n_streams);
-    std::memcpy(h + (L.sdesc - L.desc), ss.data(), sizeof(BatchScanStream) * n_streams);
-    std::memcpy(h + (L.blocks - L.desc), bl.data(), sizeof(BatchScanBlock) * bl.size());
-    if (hipMemcpyAsync(ws + L.desc, h, up, hipMemcpyHostToDevice, stream) != hipSuccess ||
+    std::memcpy(h + L.desc, d.data(), sizeof(BatchStreamDev) * n_streams);
+    if (hipMemcpyAsync(ws, h, up, hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipEventRecord(sb->done, stream) != hipSuccess) {
         std::lock_guard<std::mutex> lk(g_stage_mu);
         sb->busy = false;
         return HD_ERR_DEVICE;
     }
     uint32_t *status = reinterpret_cast<uint32_t *>(ws);
-    const BatchScanStream *ssd = reinterpret_cast<const BatchScanStream *>(ws + L.sdesc);
-    const BatchScanBlock *bld = reinterpret_cast<const BatchScanBlock *>(ws + L.blocks);
-    uint64_t *partial = reinterpret_cast<uint64_t *>(ws + L.partial);
-    hipLaunchKernelGGL(k_bscan_reduce, dim3(L.nblk_total), dim3(kScanThreads), 0, stream, ssd, bld, partial, status);
-    hipLaunchKernelGGL(k_bscan_finish, dim3(L.nblk_total), dim3(kScanThreads), 0, stream, ssd, bld, partial, status);
-    if (hipGetLastError() != hipSuccess)
-        return HD_ERR_DEVICE;
     if (items == 0)
         return HD_OK;
     BatchArgs a;
@@ -2560,10 +2501,24 @@ extern "C" uint32_t hd_decode_status_bits(const void *workspace, void *hip_strea
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     if (hipStreamSynchronize(stream) != hipSuccess)
         return 0xffffffffu;
-    uint32_t v = 0;
-    if (hipMemcpy(&v, workspace, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+    // header word 0, OR-ed with the per-wavefront slots the last decode
+    // kernel wrote (word 1 counts them; 0 for batches, reconstruction and
+    // encoding, which report in word 0 alone)
+    uint32_t head[2] = {0, 0};
+    if (hipMemcpy(head, workspace, sizeof(head), hipMemcpyDeviceToHost) != hipSuccess)
         return 0xffffffffu;
-    return v;
+    if (head[1] > kMaxSlots)
+        return 0xffffffffu;
+    uint32_t v = head[0];
+    if (head[1]) {
+        std::vector<uint32_t> slots(head[1]);
+        if (hipMemcpy(slots.data(), static_cast<const char *>(workspace) + kWsHeader, 4 * size_t(head[1]),
+                      hipMemcpyDeviceToHost) != hipSuccess)
+            return 0xffffffffu;
+        for (uint32_t e : slots)
+            v |= e;
+    }
+    return v == 0xffffffffu ? v & ~0x80000000u : v;
 }
 
 extern "C" hd_status hd_decode_status(const void *workspace, void *hip_stream)

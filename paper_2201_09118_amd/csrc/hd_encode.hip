@@ -1,6 +1,6 @@
 // Huffman encoding on the device, for gfx950: the compress side of the
 // stream format read by the decoders (Sec. II-B codewords, Sec. III-B 32-bit
-// units, Sec. III-C gap array, per-chunk codeword counts).
+// units, Sec. III-C gap array, chunk offsets).
 //
 //   k_enc_hist   histogram of the symbols: a persistent grid, counts in LDS
 //                per workgroup over many blocks, then one 64-bit atomic add
@@ -19,9 +19,8 @@
 //                the neighbour blocks (units start zeroed).  A
 //                symbol whose codeword ends at or past a subsequence boundary
 //                k*S (and starts before it) writes gap[k]; a symbol after
-//                which a chunk boundary falls records itself + 1 as that
-//                chunk's first codeword.
-//   k_enc_counts chunk_counts[c] = first[c + 1] - first[c].
+//                which a chunk boundary falls records its index + 1 as that
+//                chunk's offset (the output index of its first codeword).
 //
 // HBM bytes per symbol: 2 (plan) + 2 (write) + the bitstream (zero fill, then
 // written) + one gap byte per subsequence and 8 B per chunk.
@@ -45,14 +44,12 @@ constexpr size_t kEncHead = 256;                       // status word + total bi
 constexpr uint32_t kTabLdsSyms = 16384;                // codebook in LDS up to this alphabet
 
 struct EncWs {
-    uint32_t *status;      // byte 0
+    uint32_t *status;      // byte 0 (byte 4: zero, no decode status slots)
     uint64_t *total;       // byte 8
     uint32_t *block_bits;  // [nblk]
     uint64_t *block_off;   // [nblk]
-    uint64_t *first;       // [M + 1]: index of each chunk's first codeword
 };
 
-// Bytes up to the chunk array (what hd_encode_plan uses).
 size_t enc_ws_bytes(uint64_t n)
 {
     const uint64_t nblk = (n + kEncSyms - 1) / kEncSyms;
@@ -68,7 +65,6 @@ EncWs enc_ws(void *ws, uint64_t n)
     w.total = reinterpret_cast<uint64_t *>(p + 8);
     w.block_bits = reinterpret_cast<uint32_t *>(p + kEncHead);
     w.block_off = reinterpret_cast<uint64_t *>(p + kEncHead + ((nblk * 4 + 15) & ~uint64_t(15)));
-    w.first = reinterpret_cast<uint64_t *>(p + enc_ws_bytes(n));
     return w;
 }
 
@@ -247,7 +243,7 @@ struct WriteArgs {
     uint64_t n_words;
     uint8_t *gap;
     uint64_t K;
-    uint64_t *first;         // [M + 1]
+    uint64_t *first;         // [M + 1] chunk offsets (the caller's array)
     uint64_t M;
     const uint64_t *block_off;
     const uint64_t *total;
@@ -387,17 +383,20 @@ __global__ void __launch_bounds__(kEncBlock) k_enc_write(WriteArgs a)
         atomicOr(a.status, hd::kErrOutRange);
 }
 
-__global__ void k_enc_counts(const uint64_t *first, uint64_t M, uint32_t *counts)
+// Offsets of an empty stream: every chunk starts at output index 0.
+__global__ void k_enc_zero_offsets(uint64_t *first, uint64_t M)
 {
-    const uint64_t c = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c < M)
-        counts[c] = static_cast<uint32_t>(first[c + 1] - first[c]);
+    for (uint64_t c = threadIdx.x; c <= M; c += blockDim.x)
+        first[c] = 0;
 }
 
+// Clears the status word, the word after it (the count of decode status
+// slots, which hd_decode_status_bits reads) and the planned total.
 __global__ void k_enc_clear(uint32_t *status, uint64_t *total)
 {
     if (threadIdx.x == 0) {
-        *status = 0;
+        status[0] = 0;
+        status[1] = 0;
         *total = 0;
     }
 }
@@ -414,9 +413,7 @@ extern "C" size_t hd_encode_workspace_size(uint64_t n, uint32_t L, const hd_layo
     if (!lay || lay->subseq_bits == 0 || lay->chunk_subseqs == 0 || L == 0 || L > 32)
         return 0;
     // n * L bits bound the stream, hence the subsequence and chunk counts
-    const uint64_t k_max = (n * L + lay->subseq_bits - 1) / lay->subseq_bits;
-    const uint64_t m_max = (k_max + lay->chunk_subseqs - 1) / lay->chunk_subseqs;
-    return enc_ws_bytes(n) + (m_max + 1) * 8;
+    return enc_ws_bytes(n);
 }
 
 extern "C" hd_status hd_histogram(const uint16_t *syms, uint64_t n, uint32_t A, uint64_t *hist, void *hip_stream)
@@ -470,13 +467,13 @@ extern "C" hd_status hd_encode_bits(const void *workspace, uint64_t *n_bits, voi
 
 extern "C" hd_status hd_encode_write(const uint16_t *syms, uint64_t n, const uint8_t *lengths, const uint32_t *codes,
                                      uint32_t A, const hd_layout *lay, uint32_t *words, uint64_t n_words,
-                                     uint8_t *gap, uint64_t n_subseq, uint32_t *chunk_counts, uint64_t n_chunks,
+                                     uint8_t *gap, uint64_t n_subseq, uint64_t *chunk_offsets, uint64_t n_chunks,
                                      void *workspace, size_t ws_bytes, void *hip_stream)
 {
     if (!lay || lay->subseq_bits == 0 || lay->subseq_bits % 32 || lay->chunk_subseqs == 0)
         return HD_ERR_ARG;
-    if (!workspace || ws_bytes < enc_ws_bytes(n) + (n_chunks + 1) * 8 || !lengths || !codes || A == 0 ||
-        A > 65536 || (n && !syms) || !words || n_words < 2 || (n_subseq && !gap) || (n_chunks && !chunk_counts) ||
+    if (!workspace || ws_bytes < enc_ws_bytes(n) || !lengths || !codes || A == 0 ||
+        A > 65536 || (n && !syms) || !words || n_words < 2 || (n_subseq && !gap) || !chunk_offsets ||
         reinterpret_cast<uintptr_t>(workspace) % 16 || n_chunks != (n_subseq + lay->chunk_subseqs - 1) /
         lay->chunk_subseqs)
         return HD_ERR_ARG;
@@ -497,7 +494,7 @@ extern "C" hd_status hd_encode_write(const uint16_t *syms, uint64_t n, const uin
         a.n_words = n_words;
         a.gap = gap;
         a.K = n_subseq;
-        a.first = w.first;
+        a.first = chunk_offsets;
         a.M = n_chunks;
         a.block_off = w.block_off;
         a.total = w.total;
@@ -505,9 +502,8 @@ extern "C" hd_status hd_encode_write(const uint16_t *syms, uint64_t n, const uin
         a.vec = reinterpret_cast<uintptr_t>(syms) % 16 == 0;
         const size_t lds = A <= kTabLdsSyms ? size_t(A) * 5 : 0;
         hipLaunchKernelGGL(k_enc_write, dim3(static_cast<uint32_t>(nblk)), dim3(kEncBlock), lds, stream, a);
-        if (n_chunks)
-            hipLaunchKernelGGL(k_enc_counts, dim3(grid_of(n_chunks, 256)), dim3(256), 0, stream, w.first,
-                               n_chunks, chunk_counts);
+    } else {
+        hipLaunchKernelGGL(k_enc_zero_offsets, dim3(1), dim3(64), 0, stream, chunk_offsets, n_chunks);
     }
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }

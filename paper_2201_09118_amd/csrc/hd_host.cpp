@@ -7,8 +7,8 @@
 // can use a compact lookup table (first level + per-length limits).
 //
 // The encoder writes the stream format described in include/hd.h: 32-bit
-// units (Sec. III-B), one gap byte per subsequence (Sec. III-C) and one count
-// per chunk of subsequences (the output-index input of Sec. III-B, step 3).
+// units (Sec. III-B), one gap byte per subsequence (Sec. III-C) and the output
+// index of every chunk's first codeword (Sec. III-B, step 3, stored).
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
@@ -165,7 +165,7 @@ extern "C" hd_status hd_build_codebook(const uint64_t *hist, uint32_t A, uint32_
 extern "C" hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8_t *lengths,
                                    const uint32_t *codes, uint32_t A, uint32_t L,
                                    const hd_layout *lay, uint32_t *words, uint64_t words_cap,
-                                   uint8_t *gap, uint64_t gap_cap, uint32_t *chunk_counts,
+                                   uint8_t *gap, uint64_t gap_cap, uint64_t *chunk_offsets,
                                    uint64_t chunk_cap, hd_stream_info *info)
 {
     if (!lengths || !codes || !lay || !info || (n && !syms))
@@ -200,11 +200,13 @@ extern "C" hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8
     info->max_len = L;
     if (!words)
         return HD_OK;
-    if (words_cap < NW || gap_cap < K || chunk_cap < M || (K && (!gap || !chunk_counts)))
+    if (words_cap < NW || gap_cap < K || chunk_cap < M + 1 || !chunk_offsets || (K && !gap))
         return HD_ERR_ARG;
 
-    std::memset(chunk_counts, 0, M * sizeof(uint32_t));
+    // chunk_offsets[c]: codewords that start before chunk c (filled as each
+    // chunk's first codeword goes by; chunks without one take the next)
     const uint64_t chunk_bits = static_cast<uint64_t>(S) * C;
+    uint64_t next_chunk = 0;
     uint64_t acc = 0;       // pending bits, right-aligned
     uint32_t nacc = 0;      // number of pending bits (< 32 between symbols)
     uint64_t wi = 0;        // next unit to write
@@ -222,7 +224,8 @@ extern "C" hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8
         }
         for (; b < end; b += S)
             gap[b / S] = static_cast<uint8_t>(end - b);
-        chunk_counts[pos / chunk_bits] += 1;
+        for (; next_chunk <= pos / chunk_bits; ++next_chunk)
+            chunk_offsets[next_chunk] = i;
 
         acc = (acc << l) | codes[s];
         nacc += l;
@@ -233,10 +236,35 @@ extern "C" hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8
         acc &= (nacc ? ((uint64_t(1) << nacc) - 1) : 0);
         pos = end;
     }
+    for (; next_chunk <= M; ++next_chunk)
+        chunk_offsets[next_chunk] = n;
     if (nacc)
         words[wi++] = static_cast<uint32_t>(acc << (32 - nacc));
     for (; wi < NW; ++wi)
         words[wi] = 0;
+    return HD_OK;
+}
+
+extern "C" hd_status hd_stream_layout(uint64_t n_symbols, uint64_t n_bits, uint32_t A, uint32_t L,
+                                      const hd_layout *lay, hd_stream_info *info)
+{
+    if (!lay || !info || A == 0 || A > 65536 || L == 0 || L > 32)
+        return HD_ERR_ARG;
+    const uint32_t S = lay->subseq_bits, C = lay->chunk_subseqs;
+    if (S < 32 || S % 32 != 0 || C == 0)
+        return HD_ERR_ARG;
+    if (n_bits < n_symbols || static_cast<unsigned __int128>(n_bits) > static_cast<unsigned __int128>(L) * n_symbols)
+        return HD_ERR_CORRUPT;
+    const uint64_t K = (n_bits + S - 1) / S;
+    info->n_symbols = n_symbols;
+    info->n_bits = n_bits;
+    info->n_subseq = K;
+    info->n_chunks = (K + C - 1) / C;
+    info->n_words = K * (S / 32) + 2;
+    info->subseq_bits = S;
+    info->chunk_subseqs = C;
+    info->alphabet_size = A;
+    info->max_len = L;
     return HD_OK;
 }
 

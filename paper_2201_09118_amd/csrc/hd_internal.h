@@ -18,10 +18,10 @@ enum : uint32_t {
     kErrGapRange = 1u << 0,     // a gap byte larger than any codeword allows
     kErrBadCode = 1u << 1,      // a window matched no codeword
     kErrLaneEnd = 1u << 2,      // a subsequence ended off its successor's start
-    kErrChunkSum = 1u << 3,     // decoded count of a chunk != chunk_counts
-    kErrTotal = 1u << 4,        // chunk counts do not add up to n_symbols
+    kErrChunkSum = 1u << 3,     // decoded count of a chunk != its stored offsets
+    kErrTotal = 1u << 4,        // chunk offsets not from 0 to n_symbols (self-sync: totals)
     kErrOutRange = 1u << 5,     // an output index fell outside [0, n)
-    kErrNoSync = 1u << 6,       // self-synchronization found no consistent start
+    kErrNoSync = 1u << 6,       // the synchronized path does not end on the stream end
     kErrNoOutlier = 1u << 7,    // reconstruction: a code-0 position missing from the outlier list
 };
 

@@ -573,10 +573,14 @@ __global__ void __launch_bounds__(kLzBlock) k_lz_line_out(LzArgs a, const uint32
         atomicOr(a.status, hd::kErrNoOutlier);
 }
 
+// Clears the status word and the word after it (the count of decode status
+// slots, which hd_decode_status_bits reads; none here).
 __global__ void k_lz_clear(uint32_t *status)
 {
-    if (threadIdx.x == 0)
-        *status = 0;
+    if (threadIdx.x == 0) {
+        status[0] = 0;
+        status[1] = 0;
+    }
 }
 
 // Rows per wavefront block: 32, halved (down to 8) while the plane kernel

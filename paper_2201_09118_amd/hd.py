@@ -48,6 +48,7 @@ SIGNATURES = {
     "hd_encode_write": (C.c_int, [_vp, _u64, _vp, _vp, _u32, _vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _sz, _vp]),
     "hd_lorenzo_reconstruct": (C.c_int, [_vp, _u32, _u32, _u32, _u32, _vp, _vp, _u64, C.c_double, _vp, _vp, _vp,
                                          _sz, _vp]),
+    "hd_stream_layout": (C.c_int, [_u64, _u64, _u32, _u32, _vp, _vp]),
     "hd_status_str": (C.c_char_p, [C.c_int]),
     "hd_server_create": (C.c_int, [_sz, _u32, _u32, C.POINTER(_vp)]),
     "hd_server_destroy": (None, [_vp]),
@@ -83,7 +84,7 @@ class Tune(C.Structure):
 
 
 class DStream(C.Structure):
-    _fields_ = [("words", C.c_void_p), ("gap", C.c_void_p), ("chunk_counts", C.c_void_p),
+    _fields_ = [("words", C.c_void_p), ("gap", C.c_void_p), ("chunk_offsets", C.c_void_p),
                 ("info", StreamInfo), ("table", C.c_void_p)]
 
 
@@ -148,7 +149,7 @@ def build_codebook(hist: np.ndarray, L: int):
 class HostStream:
     words: np.ndarray
     gap: np.ndarray
-    chunk_counts: np.ndarray
+    chunk_offsets: np.ndarray      # uint64[n_chunks + 1]
     info: StreamInfo
 
     @property
@@ -172,7 +173,7 @@ def encode_ref(syms: np.ndarray, lengths: np.ndarray, codes: np.ndarray, L: int,
                             C.byref(lay), None, 0, None, 0, None, 0, C.byref(info)), "hd_encode_ref(size)")
     words = np.zeros(info.n_words, np.uint32)
     gap = np.zeros(info.n_subseq, np.uint8)
-    cc = np.zeros(info.n_chunks, np.uint32)
+    cc = np.zeros(info.n_chunks + 1, np.uint64)
     _check(L_.hd_encode_ref(_np_ptr(syms), syms.size, _np_ptr(lengths), _np_ptr(codes), lengths.size, L,
                             C.byref(lay), _np_ptr(words), words.size, _np_ptr(gap), gap.size, _np_ptr(cc),
                             cc.size, C.byref(info)), "hd_encode_ref")
@@ -217,7 +218,7 @@ class DeviceStream:
     """A stream resident in device memory (torch tensors) plus its table."""
     words: object          # torch int32 tensor (bit pattern of the uint32 units)
     gap: object            # torch uint8 tensor or None
-    chunk_counts: object   # torch int32 tensor or None
+    chunk_offsets: object  # torch int64 tensor (n_chunks + 1 entries) or None
     info: StreamInfo
     table: Table
 
@@ -226,7 +227,7 @@ class DeviceStream:
         import torch
         w = torch.from_numpy(hs.words.view(np.int32)).to(device)
         g = torch.from_numpy(hs.gap).to(device) if with_gap else None
-        c = torch.from_numpy(hs.chunk_counts.view(np.int32)).to(device) if with_gap else None
+        c = torch.from_numpy(hs.chunk_offsets.view(np.int64)).to(device) if with_gap else None
         info = StreamInfo()
         C.pointer(info)[0] = hs.info
         return cls(w, g, c, info, table)
@@ -235,8 +236,8 @@ class DeviceStream:
         d = DStream()
         d.words = self.words.data_ptr() if self.words is not None and self.words.numel() else None
         d.gap = self.gap.data_ptr() if self.gap is not None and self.gap.numel() else None
-        d.chunk_counts = (self.chunk_counts.data_ptr()
-                          if self.chunk_counts is not None and self.chunk_counts.numel() else None)
+        d.chunk_offsets = (self.chunk_offsets.data_ptr()
+                           if self.chunk_offsets is not None and self.chunk_offsets.numel() else None)
         d.info = self.info
         d.table = self.table.handle
         return d
@@ -347,7 +348,7 @@ def histogram(syms, A: int, hist=None, stream=None):
 class DeviceEncoded:
     words: object
     gap: object
-    chunk_counts: object
+    chunk_offsets: object
     n_symbols: int
     n_bits: int
     S: int
@@ -373,16 +374,23 @@ def encode_device(syms, lengths, codes, L: int, S: int = 128, chunk: int = 32, w
     bits = C.c_uint64()
     _check(lib().hd_encode_bits(_dev_ptr(workspace), C.byref(bits), _stream_handle(stream)), "hd_encode_bits")
     B = int(bits.value)
-    K = (B + S - 1) // S
-    M = (K + chunk - 1) // chunk
-    NW = K * S // 32 + 2
+    info = stream_layout(n, B, A, L, S, chunk)
+    K, M, NW = int(info.n_subseq), int(info.n_chunks), int(info.n_words)
     words = torch.empty(NW, dtype=torch.int32, device=syms.device)
     gap = torch.empty(max(K, 1), dtype=torch.uint8, device=syms.device)
-    cc = torch.empty(max(M, 1), dtype=torch.int32, device=syms.device)
+    cc = torch.empty(M + 1, dtype=torch.int64, device=syms.device)
     _check(lib().hd_encode_write(sp, n, _dev_ptr(lengths), _dev_ptr(codes), A, C.byref(lay), _dev_ptr(words), NW,
                                  _dev_ptr(gap), K, _dev_ptr(cc), M, _dev_ptr(workspace), workspace.numel(),
                                  _stream_handle(stream)), "hd_encode_write")
-    return DeviceEncoded(words, gap[:K], cc[:M], n, B, S, chunk), workspace
+    return DeviceEncoded(words, gap[:K], cc, n, B, S, chunk), workspace
+
+
+def stream_layout(n_symbols: int, n_bits: int, A: int, L: int, S: int = 128, chunk: int = 32) -> StreamInfo:
+    """hd_stream_layout: the stream-format sizes (StreamInfo) of n_symbols coded in n_bits bits."""
+    info = StreamInfo()
+    lay = Layout(S, chunk)
+    _check(lib().hd_stream_layout(n_symbols, n_bits, A, L, C.byref(lay), C.byref(info)), "hd_stream_layout")
+    return info
 
 
 def lorenzo_workspace_size(shape) -> int:

@@ -49,7 +49,7 @@ def upload(case: Case, lut_bits=0, with_gap=True, device="cuda"):
     e = case.enc
     w = torch.from_numpy(e.words.view(np.int32)).to(device)
     g = torch.from_numpy(e.gap).to(device) if with_gap else None
-    c = torch.from_numpy(e.chunk_counts.view(np.int32)).to(device) if with_gap else None
+    c = torch.from_numpy(e.chunk_offsets.view(np.int64)).to(device) if with_gap else None
     return hd.DeviceStream(w, g, c, case.info(), tab)
 
 

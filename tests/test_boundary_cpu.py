@@ -99,7 +99,7 @@ def test_encode_ref_matches_oracle(S, C):
     assert hs.n_bits == e.n_bits
     assert np.array_equal(hs.words, e.words)
     assert np.array_equal(hs.gap, e.gap)
-    assert np.array_equal(hs.chunk_counts, e.chunk_counts)
+    assert np.array_equal(hs.chunk_offsets, e.chunk_offsets)
     assert hs.info.n_subseq == e.gap.size and hs.info.n_chunks == e.chunk_counts.size
 
 
@@ -108,7 +108,7 @@ def test_encode_ref_edge_cases():
     ln = np.array([1, 1], np.uint8)
     cd = np.array([0, 1], np.uint32)
     hs = hd.encode_ref(np.zeros(0, np.uint16), ln, cd, 4)
-    assert hs.n_bits == 0 and hs.words.size == 2 and hs.gap.size == 0
+    assert hs.n_bits == 0 and hs.words.size == 2 and hs.gap.size == 0 and hs.chunk_offsets.tolist() == [0]
     with pytest.raises(hd.HDError) as ei:
         hd.encode_ref(np.array([0, 2], np.uint16), ln, cd, 4)
     assert ei.value.status == hd.ERR_SYMBOL
@@ -135,7 +135,7 @@ def test_encode_ref_edge_cases():
     e = oracle.encode(x, ln2, cd2, 64, 4)
     hs = hd.encode_ref(x, ln2, cd2, 32, 64, 4)
     assert np.array_equal(hs.words, e.words) and np.array_equal(hs.gap, e.gap)
-    assert np.array_equal(hs.chunk_counts, e.chunk_counts)
+    assert np.array_equal(hs.chunk_offsets, e.chunk_offsets)
     assert np.array_equal(oracle.decode(hs.words, hs.n_bits, x.size, ln2, cd2), x)
 
 
@@ -177,9 +177,9 @@ def test_encode_workspace_sizes_and_layout_errors():
     lay = hd.Layout(128, 32)
     n = 134_217_728
     nblk = (n + 4095) // 4096
-    k_max = (n * 24 + 127) // 128
-    m_max = (k_max + 31) // 32
-    assert L.hd_encode_workspace_size(n, 24, ctypes.byref(lay)) == 256 + nblk * 4 + nblk * 8 + (m_max + 1) * 8
+    # status/total header + per-block bits + per-block offsets (the chunk
+    # offsets go straight to the caller's array)
+    assert L.hd_encode_workspace_size(n, 24, ctypes.byref(lay)) == 256 + nblk * 4 + nblk * 8
     assert L.hd_encode_workspace_size(n, 0, ctypes.byref(lay)) == 0
     assert L.hd_encode_workspace_size(n, 33, ctypes.byref(lay)) == 0
     assert L.hd_encode_workspace_size(n, 24, ctypes.byref(hd.Layout(0, 32))) == 0
@@ -193,3 +193,24 @@ def test_encode_workspace_sizes_and_layout_errors():
     # histogram: alphabet outside [1, 65536]
     assert L.hd_histogram(dummy, 10, 0, dummy, None) == hd.ERR_ARG
     assert L.hd_histogram(dummy, 10, 65537, dummy, None) == hd.ERR_ARG
+
+
+def test_stream_layout_sizes_match_the_encoders():
+    from paper_2201_09118_amd import hd
+    rng = np.random.default_rng(21)
+    for S, C in ((32, 1), (128, 32), (256, 32), (96, 3)):
+        x = hdsynth.two_sided_geometric(rng, 30_001, 0.5, 1024)
+        ln, cd = oracle.build_codebook(x, 1024, 20)
+        e = oracle.encode(x, ln, cd, S, C)
+        info = hd.stream_layout(x.size, e.n_bits, 1024, 20, S, C)
+        assert (info.n_words, info.n_subseq, info.n_chunks) == (e.words.size, e.gap.size, e.chunk_counts.size)
+        assert e.chunk_offsets.size == info.n_chunks + 1
+    info = hd.stream_layout(0, 0, 2, 1)
+    assert (info.n_words, info.n_subseq, info.n_chunks) == (2, 0, 0)
+    for args, st in (((10, 9, 4, 4), hd.ERR_CORRUPT), ((10, 41, 4, 4), hd.ERR_CORRUPT),
+                     ((10, 20, 0, 4), hd.ERR_ARG), ((10, 20, 4, 33), hd.ERR_ARG)):
+        with pytest.raises(hd.HDError) as ei:
+            hd.stream_layout(*args)
+        assert ei.value.status == st
+    with pytest.raises(hd.HDError):
+        hd.stream_layout(10, 20, 4, 4, 48, 1)

@@ -93,7 +93,7 @@ def test_batch_reports_corrupt_stream():
     cases = _mixed_cases(43, 4, 10_000, 50_000)
     import torch
     dss = [upload(c) for c in cases]
-    dss[2].chunk_counts[0] += 1
+    dss[2].chunk_offsets[1] += 1
     outs = [torch.zeros(c.x.size + 64, dtype=torch.int16, device="cuda") for c in cases]
     ws = hd.decode_batch(dss, outs)
     assert hd.decode_status(ws) == hd.ERR_CORRUPT

@@ -218,11 +218,16 @@ def test_corrupt_metadata_is_reported():
     from paper_2201_09118_amd import hd
     x = hdsynth.two_sided_geometric(np.random.default_rng(8), 100_000, 0.5, 1024)
     case = make_case(x, 1024, 16, 128, 32)
-    # a chunk count off by one
+    # a chunk offset off by one: the chunks on both sides of it miscount
     ds = upload(case)
-    ds.chunk_counts[3] += 1
+    ds.chunk_offsets[3] += 1
     _, bits = run_decode(ds, n_out=case.x.size + 64)
-    assert bits & (1 << 3) and bits & (1 << 4)
+    assert bits & (1 << 3)
+    # offsets not ending at n
+    ds = upload(case)
+    ds.chunk_offsets[-1] += 1
+    _, bits = run_decode(ds, n_out=case.x.size + 64)
+    assert bits & (1 << 4)
     # a gap byte off by one
     ds = upload(case)
     ds.gap[10] += 1

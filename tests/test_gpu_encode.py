@@ -34,8 +34,8 @@ def _encode_gpu(x, lengths, codes, L, S, Cc):
                                L, S, Cc)
     bits = hd.decode_status_bits(ws)
     torch.cuda.synchronize()
-    return (enc.words.cpu().numpy().view(np.uint32), enc.gap.cpu().numpy(), enc.chunk_counts.cpu().numpy().view(np.uint32),
-            enc.n_bits, bits)
+    return (enc.words.cpu().numpy().view(np.uint32), enc.gap.cpu().numpy(),
+            enc.chunk_offsets.cpu().numpy().view(np.uint64), enc.n_bits, bits)
 
 
 def _check(x, lengths, codes, L, S, Cc, tag):
@@ -46,7 +46,7 @@ def _check(x, lengths, codes, L, S, Cc, tag):
     assert B == e.n_bits, tag
     assert np.array_equal(w, e.words), tag
     assert np.array_equal(g, e.gap), tag
-    assert np.array_equal(c, e.chunk_counts), tag
+    assert np.array_equal(c, e.chunk_offsets), tag
 
 
 def _book(x, A, L):
@@ -108,9 +108,9 @@ def test_encode_config2_full_size_and_decode_back():
     # the device-encoded stream decodes back on the device
     xs = _dev(x, np.int16)
     enc, _ = hd.encode_device(xs, _dev(ln, np.uint8), _dev(cd.astype(np.uint32), np.int32), 24, 128, 32)
-    info = hd.StreamInfo(x.size, enc.n_bits, enc.words.numel(), enc.gap.numel(), enc.chunk_counts.numel(),
+    info = hd.StreamInfo(x.size, enc.n_bits, enc.words.numel(), enc.gap.numel(), enc.chunk_offsets.numel() - 1,
                          128, 32, 1024, 24)
-    ds = hd.DeviceStream(enc.words, enc.gap, enc.chunk_counts, info, hd.Table(ln, cd, 24))
+    ds = hd.DeviceStream(enc.words, enc.gap, enc.chunk_offsets, info, hd.Table(ln, cd, 24))
     out = torch.empty(x.size, dtype=torch.int16, device="cuda")
     ws = hd.decode(ds, out, hd.MODE_GAP)
     assert hd.decode_status_bits(ws) == 0
@@ -133,7 +133,7 @@ def test_empty_input():
     codes = oracle.canonical_codes(lengths)
     w, g, c, B, bits = _encode_gpu(np.zeros(0, np.uint16), lengths, codes, 1, 128, 32)
     e = oracle.encode(np.zeros(0, np.uint16), lengths, codes, 128, 32)
-    assert B == 0 and bits == 0 and np.array_equal(w, e.words) and g.size == e.gap.size and c.size == e.chunk_counts.size
+    assert B == 0 and bits == 0 and np.array_equal(w, e.words) and g.size == e.gap.size and c.tolist() == [0]
 
 
 def test_bad_layout_rejected():

@@ -155,7 +155,7 @@ def test_single_symbol_selfsync():
     _check_ss(make_case(np.full(50_000, 9, np.uint16), 16, 4, 128, 32))
 
 
-def test_selfsync_ignores_gap_and_chunk_counts():
+def test_selfsync_ignores_gap_and_chunk_offsets():
     """Self-sync reads neither metadata array: garbage there changes nothing."""
     import torch
     from paper_2201_09118_amd import hd
@@ -163,7 +163,7 @@ def test_selfsync_ignores_gap_and_chunk_counts():
     case = make_case(x, 1024, 20, 128, 32)
     ds = upload(case)
     ds.gap.fill_(255)
-    ds.chunk_counts.fill_(7)
+    ds.chunk_offsets.fill_(7)
     out = torch.empty(x.size, dtype=torch.int16, device="cuda")
     ws = hd.decode(ds, out, hd.MODE_SELF_SYNC)
     assert hd.decode_status(ws) == hd.OK

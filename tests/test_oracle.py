@@ -77,6 +77,7 @@ def test_figure1_encoder_bits_and_forward_gap():
     assert unpack_bits(e.words, e.n_bits) == g["bits"][0][0]
     assert e.gap.tolist() == [int(v) for v in g["gap_forward"][0]]
     assert e.chunk_counts.tolist() == [int(v) for v in g["counts_forward"][0]]
+    assert e.chunk_offsets.tolist() == [0, 4, 8, 12, 15]
 
 
 def test_figure1_backward_gap_is_the_printed_one():
@@ -337,6 +338,12 @@ def test_encoder_layout_matches_independent_recomputation(S, C):
     assert np.array_equal(e.gap, gap)
     assert np.array_equal(e.chunk_counts.astype(np.int64), cc)
     assert e.chunk_counts.sum() == x.size
+    # stored offsets: the output index of each chunk's first codeword = the
+    # number of codeword starts before the chunk's first bit (brute force),
+    # then n
+    starts = np.concatenate([[0], np.cumsum(ln[x].astype(np.int64))])[:-1]
+    want_off = [int((starts < c * C * S).sum()) for c in range(M)] + [x.size]
+    assert e.chunk_offsets.tolist() == want_off
     assert e.gap[0] == 0 and int(e.gap.max()) < int(ln.max())
     tail = unpack_bits(e.words, e.words.size * 32)[B:]
     assert set(tail) <= {"0"}
@@ -365,6 +372,7 @@ def test_empty_stream():
     cd = np.array([0, 1], np.uint32)
     e = oracle.encode(np.zeros(0, np.uint16), ln, cd)
     assert e.n_bits == 0 and e.gap.size == 0 and e.chunk_counts.size == 0 and e.words.size == 2
+    assert e.chunk_offsets.tolist() == [0]
     assert oracle.decode(e.words, 0, 0, ln, cd).size == 0
 
 
@@ -477,6 +485,6 @@ def test_chunk_parallel_decode_round_trips(threads):
     x = (512 + rng.integers(-60, 61, 70001)).astype(np.uint16)
     ln, cd = oracle.build_codebook(x, 1024, 16)
     e = oracle.encode(x, ln, cd, 128, 32)
-    y = oracle.decode_chunks_parallel(e.words, e.n_bits, x.size, ln, cd, e.gap, e.chunk_counts, 128, 32,
+    y = oracle.decode_chunks_parallel(e.words, e.n_bits, x.size, ln, cd, e.gap, e.chunk_offsets, 128, 32,
                                       threads)
     assert np.array_equal(y, x)
