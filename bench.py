@@ -86,7 +86,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["gap", "selfsync", "both"], default="both")
-    ap.add_argument("--workload", choices=["config1", "config2", "config3", "batch", "serve", "sz", "sz1d", "encode", "lds_sweep"], default="config2")
+    ap.add_argument("--workload", choices=["config1", "config2", "config3", "batch", "serve", "sz", "sz1d", "encode", "lds_sweep",
+                             "cr_classes"], default="config2")
     ap.add_argument("--batch-streams", type=int, default=256)
     ap.add_argument("--batch-lo", type=int, default=1 << 16)
     ap.add_argument("--batch-hi", type=int, default=1 << 26)
@@ -110,6 +111,13 @@ def main():
                     help="threads of the chunk-parallel CPU baseline (capped by the CPUs this process may use)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM traffic counters)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="default line: skip the batched 256-stream measurement")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="default line: skip the served-vs-serial measurement")
+    ap.add_argument("--line-serve-rate", type=float, default=500.0,
+                    help="default line: the one Poisson rate of the served measurement (requests/s)")
+    ap.add_argument("--line-serve-seconds", type=float, default=6.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -134,6 +142,8 @@ def main():
         return bench_sz1d(args)
     if args.workload == "lds_sweep":
         return bench_lds_sweep(args)
+    if args.workload == "cr_classes":
+        return bench_cr_classes(args)
 
     t0 = time.time()
     w = workload(args.workload)
@@ -339,6 +349,33 @@ def main():
                       "decode_run_ms": round(r["k_ms"], 5), "prepare_ms": round(r["ms_step"] - r["k_ms"], 5),
                       "warm": r["warm"], "cold": r["cold"], "verified": r["verified"]} for m, r in res.items()},
     }
+    # the rest of the metric: batched speedup on the 256-stream batch, and
+    # served p50/p99 against a serial server on the serving pool
+    del out, tab
+    torch.cuda.empty_cache()
+    if args.workload == "config2" and not args.calibrate_copy:
+        if not args.no_batch:
+            t0 = time.time()
+            b = batch_measure(args)
+            rec["batched"] = {k: b[k] for k in ("batched_speedup", "plain_back_to_back", "batched", "config",
+                                                "autotuner_classes", "layouts", "verified")}
+            rec["batched_speedup"] = b["batched_speedup"]
+            rec["verified"] = rec["verified"] and b["verified"]
+            log(f"batched: speedup {b['batched_speedup']} in {time.time() - t0:.1f}s")
+            torch.cuda.empty_cache()
+        if not args.no_serve:
+            t0 = time.time()
+            sargs = argparse.Namespace(**vars(args))
+            sargs.serve_rates = str(args.line_serve_rate)
+            sargs.serve_seconds = args.line_serve_seconds
+            sv = serve_measure(sargs)
+            pr = sv["per_rate"][0]
+            rec["served"] = {"pool_streams": sv["config"]["pool_streams"], "budget_gb": sv["config"]["budget_gb"],
+                             "poisson": pr, "burst": sv["burst"], "verified": sv["verified"]}
+            rec["p50_ms"] = pr["served"]["p50_ms"]
+            rec["p99_ms"] = pr["served"]["p99_ms"]
+            rec["verified"] = rec["verified"] and sv["verified"]
+            log(f"served: {pr} burst {sv['burst']} in {time.time() - t0:.1f}s")
     verified = rec["verified"]
     print(json.dumps(rec), flush=True)
     if not verified:
@@ -744,6 +781,136 @@ def bench_lds_sweep(args):
         sys.exit(1)
 
 
+def bench_cr_classes(args):
+    """The paper's Algorithm 2 (per-tile compression-ratio classes, one launch
+    per class on separate streams, hd_decode_cr_classes) against the
+    persistent single launch (library default and hd_autotune's pick) and a
+    brute-force staging sweep, on the config-2 stream; then on the 256-stream
+    batch, Alg. 2 per stream (the paper's per-call use) against back-to-back
+    plain decodes and the one batched launch.  Every output verified."""
+    import torch
+    import hdsynth
+    from paper_2201_09118_amd import hd
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    x = hdsynth.config2_symbols()
+    n = int(x.size)
+    ln, cd = hd.build_codebook(np.bincount(x, minlength=1024).astype(np.uint64), 24)
+    hs = hd.encode_ref(x, ln, cd, 24, 128, 32)
+    tab = hd.Table(ln, cd, 24)
+    ds = hd.DeviceStream.from_host(hs, tab, device=dev)
+    out = torch.empty(n, dtype=torch.int16, device=dev)
+    xs = torch.from_numpy(x.view(np.int16)).to(dev)
+    ok = True
+
+    def ev_ms(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    ws = hd.alloc_workspace(hd.decode_workspace_size(ds), dev)
+    out.fill_(-1)
+    hd.decode(ds, out, hd.MODE_GAP, None, ws, stream)
+    ok &= hd.decode_status(ws, stream) == hd.OK and torch.equal(out, xs)
+    t_default = ev_ms(lambda: hd.decode(ds, out, hd.MODE_GAP, None, ws, stream), args.steps)
+    tuned, _ = hd.autotune(ds, out)
+    t_tuned = ev_ms(lambda: hd.decode(ds, out, hd.MODE_GAP, tuned, ws, stream), args.steps)
+    sweep = {}
+    for st in list(range(1024, 8193, 512)):
+        try:
+            sweep[st] = ev_ms(lambda: hd.decode(ds, out, hd.MODE_GAP, hd.Tune(0, st, 0, 0), ws, stream), 5)
+        except hd.HDError:
+            continue
+    best_st = min(sweep, key=sweep.get)
+    # Alg. 2: the call itself waits for the histogram (host round trip)
+    cws, rep = hd.decode_cr_classes(ds, out, None, stream)
+    out.fill_(-1)
+    cws, rep = hd.decode_cr_classes(ds, out, cws, stream)
+    ok &= hd.decode_status(cws, stream) == hd.OK and torch.equal(out, xs)
+    tot, cls = [], []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, r = hd.decode_cr_classes(ds, out, cws, stream)
+        torch.cuda.synchronize()
+        tot.append((time.perf_counter() - t0) * 1e3)
+        cls.append(r["classify_us"] * 1e-3)
+    t_alg2, t_cls = float(np.median(tot)), float(np.median(cls))
+    log(f"config2: default {t_default:.4f} ms, tuned {t_tuned:.4f}, sweep best {best_st} {sweep[best_st]:.4f}, "
+        f"alg2 {t_alg2:.4f} (classification {t_cls:.4f}) {rep}")
+    c2 = {"default_ms": round(t_default, 5), "autotuned_ms": round(t_tuned, 5),
+          "autotuned": {"waves_per_group": tuned.waves_per_group, "stage_symbols": tuned.stage_symbols},
+          "sweep_best": {"stage_symbols": best_st, "ms": round(sweep[best_st], 5)},
+          "sweep_ms": {str(k): round(v, 5) for k, v in sweep.items()},
+          "alg2_ms": round(t_alg2, 5), "alg2_classification_ms": round(t_cls, 5),
+          "alg2_without_classification_ms": round(t_alg2 - t_cls, 5), "alg2_report": rep,
+          "alg2_vs_default": round(t_alg2 / t_default, 3)}
+    del ds, ws, cws, out, xs, tab
+    torch.cuda.empty_cache()
+
+    # the 256-stream batch, default layout (128, 32) and tables
+    specs = hdsynth.batch_stream_specs(args.batch_streams, args.batch_lo, args.batch_hi)
+    xs4, books, _, hss = _prepare_streams(specs)
+    n_tot = sum(v.size for v in xs4)
+    dss = [hd.DeviceStream.from_host(h, hd.Table(l, c, 24), device=dev) for h, (l, c) in zip(hss, books)]
+    outs = [torch.empty(max(v.size, 8), dtype=torch.int16, device=dev) for v in xs4]
+    wss = [hd.alloc_workspace(hd.decode_workspace_size(d), dev) for d in dss]
+    cwss = [hd.decode_cr_classes(d, o, None, stream)[0] for d, o in zip(dss, outs)]
+    bws = hd.alloc_workspace(hd.decode_batch_workspace_size(dss), dev)
+
+    def plain():
+        for d, o, w in zip(dss, outs, wss):
+            hd.decode(d, o, hd.MODE_GAP, None, w, stream)
+
+    def batched():
+        hd.decode_batch(dss, outs, hd.MODE_GAP, None, bws, stream)
+
+    def alg2():
+        for d, o, w in zip(dss, outs, cwss):
+            hd.decode_cr_classes(d, o, w, stream)
+
+    res4 = {}
+    for name, fn in (("plain", plain), ("batched", batched), ("alg2_per_stream", alg2)):
+        for o in outs:
+            o.fill_(-1)
+        fn()
+        torch.cuda.synchronize()
+        good = all(np.array_equal(o[:v.size].cpu().numpy().view(np.uint16), v) for o, v in zip(outs, xs4))
+        ok &= good
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        res4[name] = {"ms": round(float(np.median(ts)), 4),
+                      "gbs": round(2.0 * n_tot / (np.median(ts) * 1e-3) / 1e9, 2), "verified": bool(good)}
+        log(f"config4 {name}: {res4[name]}")
+    rec = {
+        "metric": "decode ms: the paper's Algorithm 2 (CR classes, per-class launches) vs the persistent launch",
+        "value": c2["alg2_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": c2["alg2_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u16", "data": "synthetic",
+        "config": {"workload": "cr_classes", "config2_symbols": n, "config4_streams": len(dss),
+                   "config4_symbols": int(n_tot)},
+        "config2": c2, "config4": res4, "verified": bool(ok),
+    }
+    print(json.dumps(rec), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
 def oracle_book(x, A, L):
     import oracle
     ln = oracle.code_lengths(oracle.histogram(x, A), L)
@@ -802,6 +969,13 @@ def _time_ms(fn, reps=3):
 
 
 def bench_batch(args):
+    rec = batch_measure(args)
+    print(json.dumps(rec), flush=True)
+    if not rec["verified"]:
+        sys.exit(1)
+
+
+def batch_measure(args):
     """256 streams, log-uniform sizes, own codebooks: one batched persistent
     launch (autotuned per stream class) against back-to-back plain decodes."""
     import hdsynth
@@ -876,12 +1050,18 @@ def bench_batch(args):
         "autotuner_classes": len(tuner.cache), "layouts": [list(v) for v in sorted(set(layouts))],
         "verified": bool(ok),
     }
-    print(json.dumps(rec), flush=True)
-    if not ok:
-        sys.exit(1)
+    del tuned, plain, outs, wss, bws
+    return rec
 
 
 def bench_serve(args):
+    rec = serve_measure(args)
+    print(json.dumps(rec), flush=True)
+    if not rec["verified"]:
+        sys.exit(1)
+
+
+def serve_measure(args):
     """Served decode: Poisson arrivals per rate against a serial plain-decode
     server on the same trace, plus a burst; outputs spot-checked."""
     import hdsynth
@@ -942,9 +1122,8 @@ def bench_serve(args):
         "table_cache": {"hits": cache.hits, "misses": cache.misses},
         "verified": not bad,
     }
-    print(json.dumps(rec), flush=True)
-    if bad:
-        sys.exit(1)
+    del pool, outs, wss
+    return rec
 
 
 if __name__ == "__main__":

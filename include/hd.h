@@ -274,6 +274,41 @@ hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_streams, uint16_
                           void *hip_stream);
 
 /*
+ * The paper's shared-memory optimization, literally (Sec. IV-C, Algorithm 2),
+ * kept as an ablation beside hd_decode's single persistent launch.  Gap mode
+ * only.  Each wavefront tile (64 subsequences) is a "sequence": its
+ * compression ratio (16 bits per symbol over its input bits; the symbol count
+ * comes from the stored chunk offsets) is classified into T_high + 1 groups,
+ * (0,1], ..., (T_high - 1, T_high] and above T_high; on the device the
+ * classes are histogrammed and the tile indices key-value sorted by class;
+ * the histogram is copied to the host (the call waits for hip_stream here),
+ * which prefix-sums it and launches one decode kernel per non-empty class on
+ * its own library-owned stream (default priority), each with the staging of
+ * its class's upper bound (4 S c + 64 symbols per tile; the last class takes
+ * T_high's and writes larger tiles in passes).  T_high is the largest class
+ * whose layout still keeps a quarter of a CU's wavefront slots resident (the
+ * paper's 25 % occupancy rule).  hip_stream waits for every class launch, so
+ * later work on it is ordered after the decode.  The status word
+ * (hd_decode_status) covers all launches.  *report (may be NULL) receives
+ * T_high, the host time from entry until the histogram is on the host
+ * (classification overhead, including the wait for earlier work on
+ * hip_stream) and, per class, the tiles, staging and waves per workgroup.
+ * Same argument errors as hd_decode.
+ */
+typedef struct {
+    uint32_t t_high;
+    uint32_t launches;
+    double classify_us;
+    uint32_t tiles[17];
+    uint32_t stage_symbols[17];
+    uint32_t waves_per_group[17];
+} hd_cr_classes;
+
+hd_status hd_decode_cr_classes_workspace_size(const hd_dstream *s, size_t *bytes);
+hd_status hd_decode_cr_classes(const hd_dstream *s, uint16_t *out, void *workspace, size_t ws_bytes,
+                               void *hip_stream, hd_cr_classes *report);
+
+/*
  * Decode-parameter autotuning on a sample stream.  The paper tunes the
  * shared-memory buffer per call from each sequence's compression ratio
  * (Sec. IV-C, Alg. 2, Table I) and compares against a brute-force sweep;

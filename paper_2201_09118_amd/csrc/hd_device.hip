@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -781,6 +782,11 @@ struct GapArgs {
     uint32_t *head;
     uint32_t *slots;
     uint32_t own_head;           // gap mode: the kernel also writes head[0] and checks the offsets
+    uint32_t *direct;            // instead of head/slots: a caller-zeroed word (pinned host memory)
+                                 // that receives a wavefront's nonzero error bits by a plain store
+    uint32_t direct_atomic;      // direct is device memory: OR the bits in atomically instead
+    const uint32_t *list;        // when set: decode only tiles list[0 .. n_list) (one class of Alg. 2)
+    uint64_t n_list;
     TableView tab;
 };
 
@@ -995,9 +1001,11 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
     // 2. count pass (positions relative to the lane's subsequence start)
     const uint32_t re = act ? (last ? sd.last_bits : S) : 0u;
     uint32_t rs = gk;
-    if (gk >= 32) {
+    // a gap byte past any codeword, or a first subsequence not starting on
+    // the stream's first bit
+    if (gk >= 32 || (t == 0 && l == 0 && gk != 0)) {
         err |= kErrGapRange;
-        rs = re;
+        rs = gk >= 32 ? re : rs;
     }
     if (rs > re)
         rs = re;
@@ -1070,7 +1078,7 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
 // rest of a lane is walked.
 constexpr int kLogIters = 12;
 
-template <bool PAIR, uint32_t MAXU>
+template <bool PAIR, uint32_t MAXU, bool LISTED = false>
 __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -1097,21 +1105,39 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
     if (a.own_head && blockIdx.x == 0 && threadIdx.x == 0 && (sd.chunk_off[0] != 0 || sd.chunk_off[sd.M] != sd.n))
         err |= kErrTotal;
     // Tile inputs travel through registers one tile ahead: while tile t is
-    // decoded, the inputs of the wavefront's next tile are in flight.
+    // decoded, the inputs of the wavefront's next tile are in flight.  The
+    // wavefront walks positions i, i + stride, ... of the tile sequence (all
+    // tiles, or a list of them); past its end the tile index is ntiles.
+    // (the list form is a separate instantiation: it costs the plain form
+    // two registers, which would cut its occupancy)
+    const uint64_t niter = LISTED ? a.n_list : ntiles;
+    auto tile_at = [&](uint64_t j) -> uint64_t { return LISTED ? (j >= niter ? ntiles : a.list[j]) : j; };
     TileInT<MAXU> in;
-    uint64_t t = static_cast<uint64_t>(blockIdx.x) * wpg + wv;
+    uint64_t i = static_cast<uint64_t>(blockIdx.x) * wpg + wv;
+    uint64_t t = tile_at(i);
     in.load(sd, t, ntiles, lane);
-    for (; t < ntiles; t += tstride) {
+    for (; i < niter; i += tstride) {
         const bool act = (t << 6) + lane < sd.K;
         in.store_units(TTl, wps, act);
         const uint32_t gk = in.gk, gn = in.gn;
         const uint64_t c_lo = in.c_lo, c_hi = in.c_hi;
-        in.load(sd, t + tstride, ntiles, lane);
+        const uint64_t tn = tile_at(i + tstride);
+        in.load(sd, tn, ntiles, lane);
         wave_lds_sync();
         decode_tile<PAIR, PAIR ? kLogIters : 0>(sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, g, sh,
                                                 err);
+        t = tn;
     }
     err = wave_or(err);
+    if (a.direct) {
+        if (lane == 0 && err) {
+            if (a.direct_atomic)
+                atomicOr(a.direct, err);
+            else
+                *a.direct = err;
+        }
+        return;
+    }
     if (lane == 0)
         a.slots[blockIdx.x * wpg + wv] = err;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1502,6 +1528,105 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
 }
 
 // ------------------------------------------------------------------------
+// The paper's Algorithm 2, literally: compression-ratio classes of tiles
+// ------------------------------------------------------------------------
+//
+// Sec. IV-C, Alg. 2: every sequence's compression ratio (known from an
+// earlier phase -- here the stored chunk offsets give each wavefront tile's
+// symbol count) is classified into T_high + 1 groups, (0,1], (1,2], ...,
+// (T_high - 1, T_high] and (T_high, 16]; the classes are histogrammed and
+// the tile indices key-value sorted by class on the device; the histogram
+// goes to the host, which prefix-sums it and launches one decode kernel per
+// non-empty class, each with a staging buffer sized for its class's upper
+// bound, on its own stream.  Kept as an ablation beside the persistent
+// single-launch decode.
+
+constexpr uint32_t kCrMaxClasses = 17;      // T_high <= 16, plus the class above it
+
+struct CrArgs {
+    const uint64_t *chunk_off;
+    uint64_t ntiles, M, n, B;
+    uint32_t S, Cl, t_high;
+    uint32_t *cls;           // [ntiles] class of each tile (0-based)
+    uint32_t *hist;          // [kCrMaxClasses]
+    uint32_t *cursor;        // [kCrMaxClasses]
+    uint32_t *order;         // [ntiles] tile indices sorted by class
+    uint32_t *head;          // status header (word 0 cleared here, word 1 = 0: no slots)
+};
+
+__global__ void k_cr_clear(CrArgs a)
+{
+    const uint32_t i = threadIdx.x;
+    if (i < kCrMaxClasses) {
+        a.hist[i] = 0;
+        a.cursor[i] = 0;
+    }
+    if (i == 0) {
+        // the stored offsets must start at 0 and end at n
+        a.head[0] = (a.chunk_off[0] != 0 || a.chunk_off[a.M] != a.n) ? kErrTotal : 0u;
+        a.head[1] = 0;
+    }
+}
+
+// ClassifyCR + ParHistogram: a tile's compression ratio is its output bits
+// (16 per symbol) over its input bits; class c (1-based) holds ratios in
+// (c - 1, c], the last class everything above T_high.
+__global__ __launch_bounds__(256) void k_cr_classify(CrArgs a)
+{
+    __shared__ uint32_t h[kCrMaxClasses];
+    if (threadIdx.x < kCrMaxClasses)
+        h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < a.ntiles) {
+        const uint64_t c0 = (t << 6) >> a.Cl, c1 = min(((t + 1) << 6) >> a.Cl, a.M);
+        const uint64_t count = a.chunk_off[c1] - a.chunk_off[c0];
+        const uint64_t bits = min(uint64_t(64) * a.S, a.B - (t << 6) * a.S);
+        // ceil(16 count / bits), at least 1, classes above T_high merged
+        const uint64_t cr = (16 * count + bits - 1) / max(bits, uint64_t(1));
+        const uint32_t c = static_cast<uint32_t>(min<uint64_t>(max<uint64_t>(cr, 1), a.t_high + 1)) - 1;
+        a.cls[t] = c;
+        atomicAdd(&h[c], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kCrMaxClasses && h[threadIdx.x])
+        atomicAdd(&a.hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// ParKeyValueSort of (class, tile index) by class: a counting sort.  Each
+// wavefront takes one atomic slot range per class present among its lanes
+// (order within a class is not kept: it only affects scheduling).
+__global__ __launch_bounds__(256) void k_cr_sort(CrArgs a)
+{
+    __shared__ uint32_t start[kCrMaxClasses];
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (uint32_t c = 0; c < kCrMaxClasses; ++c) {
+            start[c] = acc;
+            acc += a.hist[c];
+        }
+    }
+    __syncthreads();
+    const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool act = t < a.ntiles;
+    const uint32_t c = act ? a.cls[t] : kCrMaxClasses;
+    uint64_t left = __builtin_amdgcn_ballot_w64(act);
+    while (left) {
+        const uint32_t cc = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(c), __builtin_ctzll(left)));
+        const uint64_t mine = __builtin_amdgcn_ballot_w64(act && c == cc);
+        const uint32_t lane = threadIdx.x & 63;
+        const uint32_t rank = static_cast<uint32_t>(__builtin_popcountll(mine & ((uint64_t(1) << lane) - 1)));
+        uint32_t base = 0;
+        if (lane == static_cast<uint32_t>(__builtin_ctzll(mine)))
+            base = atomicAdd(&a.cursor[cc], static_cast<uint32_t>(__builtin_popcountll(mine)));
+        base = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(base), __builtin_ctzll(mine)));
+        if (act && c == cc)
+            a.order[start[cc] + base + rank] = static_cast<uint32_t>(t);
+        left &= ~mine;
+    }
+}
+
+// ------------------------------------------------------------------------
 // Batched persistent decode: many streams, one launch
 // ------------------------------------------------------------------------
 //
@@ -1533,7 +1658,8 @@ struct BatchArgs {
     const BatchStreamDev *streams;
     uint32_t n_streams;
     uint64_t n_items;
-    uint32_t *status;
+    uint32_t *status;            // device word OR-ed atomically, or (direct) a caller-zeroed word
+    uint32_t direct;             // status is pinned host memory: a nonzero error is stored, not OR-ed
     uint32_t S_alloc, stage_alloc, k1_alloc;
 };
 
@@ -1606,8 +1732,12 @@ __global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
         }
         si = nsi;
     }
-    if (err)
-        atomicOr(a.status, err);
+    if (err) {
+        if (a.direct)
+            *a.status = err;
+        else
+            atomicOr(a.status, err);
+    }
 }
 
 }  // namespace
@@ -2073,20 +2203,19 @@ extern "C" hd_status hd_decode_prepare(const hd_dstream *s, hd_mode m, const hd_
     return enqueue_chunk_scan(sw.tot, nt, i.n_symbols, w.off, w.partial, w.status, stream);
 }
 
-extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
-                                   void *workspace, size_t ws_bytes, void *hip_stream)
+namespace {
+
+// The decode-and-write launch of a checked call.  direct: a caller-zeroed
+// status word (gap mode only; the workspace is then not used).
+hd_status run_decode_kernel(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune, void *workspace,
+                            uint32_t *direct, hipStream_t stream)
 {
-    hd_status st = check_call(s, m, tune, workspace, ws_bytes);
-    if (st != HD_OK)
-        return st;
-    if ((s->info.n_symbols && !out) || reinterpret_cast<uintptr_t>(out) % 16 != 0)
-        return HD_ERR_ARG;
+    hd_status st = HD_OK;
     const hd_stream_info &i = s->info;
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const bool ss = m == HD_MODE_SELF_SYNC;
     const uint64_t M = ss ? ceil_div(i.n_subseq, 64) : i.n_chunks;
     // (an empty stream still launches the kernel: it writes the status)
-    const WsView w = ws_view(workspace, M);
+    const WsView w = workspace ? ws_view(workspace, M) : WsView{nullptr, nullptr, nullptr, nullptr};
     Plan p;
     st = make_plan(s, tune, &p);
     if (st != HD_OK)
@@ -2108,11 +2237,39 @@ extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m
     a.head = w.status;
     a.slots = w.slots;
     a.own_head = ss ? 0u : 1u;
+    a.direct = direct;
+    a.direct_atomic = 0;
+    a.list = nullptr;
+    a.n_list = 0;
     a.tab = view_of(s->table);
     const bool small = i.subseq_bits <= 32 * kSmallUnits;
     if (s->table->pair)
         return small ? launch_gap<true, kSmallUnits>(a, p, stream) : launch_gap<true, kMaxUnitsPerLane>(a, p, stream);
     return small ? launch_gap<false, kSmallUnits>(a, p, stream) : launch_gap<false, kMaxUnitsPerLane>(a, p, stream);
+}
+
+}  // namespace
+
+extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
+                                   void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    hd_status st = check_call(s, m, tune, workspace, ws_bytes);
+    if (st != HD_OK)
+        return st;
+    if ((s->info.n_symbols && !out) || reinterpret_cast<uintptr_t>(out) % 16 != 0)
+        return HD_ERR_ARG;
+    return run_decode_kernel(s, out, m, tune, workspace, nullptr, static_cast<hipStream_t>(hip_stream));
+}
+
+hd_status hd::decode_gap_direct(const hd_dstream *s, uint16_t *out, uint32_t *status_word, void *hip_stream)
+{
+    hd_status st = check_stream(s, HD_MODE_GAP);
+    if (st != HD_OK)
+        return st;
+    if (!status_word || (s->info.n_symbols && !out) || reinterpret_cast<uintptr_t>(out) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(s->words) % 16 != 0)
+        return HD_ERR_ARG;
+    return run_decode_kernel(s, out, HD_MODE_GAP, nullptr, nullptr, status_word, static_cast<hipStream_t>(hip_stream));
 }
 
 extern "C" hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
@@ -2127,6 +2284,238 @@ extern "C" hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, co
     if (st != HD_OK)
         return st;
     return hd_decode_run(s, out, m, tune, workspace, ws_bytes, hip_stream);
+}
+
+// ------------------------------------------------------------------------
+// Algorithm 2 host side: classes, per-class launches on separate streams
+// ------------------------------------------------------------------------
+
+namespace {
+
+// Library-owned streams of the per-class launches (default priority, one
+// per class, created once per device) and their completion events.
+struct CrStreams {
+    hipStream_t s[kCrMaxClasses];
+    hipEvent_t ev[kCrMaxClasses];
+    bool ok = false;
+};
+
+std::mutex g_cr_mu;
+CrStreams g_cr[64];
+
+const CrStreams *cr_streams()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_cr_mu);
+    CrStreams &c = g_cr[dev];
+    if (!c.ok) {
+        for (uint32_t i = 0; i < kCrMaxClasses; ++i)
+            if (hipStreamCreateWithFlags(&c.s[i], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&c.ev[i], hipEventDisableTiming) != hipSuccess)
+                return nullptr;
+        c.ok = true;
+    }
+    return &c;
+}
+
+struct CrWs {
+    uint32_t *head, *cls, *order, *hist, *cursor;
+};
+
+size_t cr_ws_bytes(uint64_t ntiles)
+{
+    return kWsStatusBytes + 2 * align_up(4 * ntiles, 256) + 2 * 256;
+}
+
+CrWs cr_ws(void *workspace, uint64_t ntiles)
+{
+    char *p = static_cast<char *>(workspace);
+    CrWs w;
+    w.head = reinterpret_cast<uint32_t *>(p);
+    p += kWsStatusBytes;
+    w.cls = reinterpret_cast<uint32_t *>(p);
+    p += align_up(4 * ntiles, 256);
+    w.order = reinterpret_cast<uint32_t *>(p);
+    p += align_up(4 * ntiles, 256);
+    w.hist = reinterpret_cast<uint32_t *>(p);
+    w.cursor = reinterpret_cast<uint32_t *>(p + 256);
+    return w;
+}
+
+// Staging of class c (1-based): a tile of 64 subsequences of S bits at a
+// compression ratio of at most c holds at most 4 S c symbols (+ 64 for the
+// alignment of the first 16-byte group).
+uint32_t cr_stage(uint32_t S, uint32_t c)
+{
+    return std::min<uint32_t>(16384, (4 * S * c + 64 + 63) / 64 * 64);
+}
+
+template <bool PAIR, uint32_t MAXU>
+hd_status launch_listed(const GapArgs &a, const Plan &p, hipStream_t stream)
+{
+    const void *f = reinterpret_cast<const void *>(&k_decode_gap<PAIR, MAXU, true>);
+    if (!allow_full_lds(f))
+        return HD_ERR_DEVICE;
+    hipLaunchKernelGGL((k_decode_gap<PAIR, MAXU, true>), dim3(p.grid), dim3(p.wpg * 64), p.lds_bytes, stream, a);
+    return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
+}
+
+const void *listed_kernel(bool pair, uint32_t S)
+{
+    const bool small = S <= 32 * kSmallUnits;
+    if (pair)
+        return small ? reinterpret_cast<const void *>(&k_decode_gap<true, kSmallUnits, true>)
+                     : reinterpret_cast<const void *>(&k_decode_gap<true, kMaxUnitsPerLane, true>);
+    return small ? reinterpret_cast<const void *>(&k_decode_gap<false, kSmallUnits, true>)
+                 : reinterpret_cast<const void *>(&k_decode_gap<false, kMaxUnitsPerLane, true>);
+}
+
+}  // namespace
+
+extern "C" hd_status hd_decode_cr_classes_workspace_size(const hd_dstream *s, size_t *bytes)
+{
+    if (!bytes)
+        return HD_ERR_ARG;
+    hd_status st = check_stream(s, HD_MODE_GAP);
+    if (st != HD_OK)
+        return st;
+    *bytes = cr_ws_bytes(ceil_div(s->info.n_subseq, 64));
+    return HD_OK;
+}
+
+extern "C" hd_status hd_decode_cr_classes(const hd_dstream *s, uint16_t *out, void *workspace, size_t ws_bytes,
+                                          void *hip_stream, hd_cr_classes *report)
+{
+    size_t need = 0;
+    hd_status st = hd_decode_cr_classes_workspace_size(s, &need);
+    if (st != HD_OK)
+        return st;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 || ws_bytes < need ||
+        reinterpret_cast<uintptr_t>(s->words) % 16 || (s->info.n_symbols && !out) ||
+        reinterpret_cast<uintptr_t>(out) % 16)
+        return HD_ERR_ARG;
+    const hd_stream_info &i = s->info;
+    const uint64_t nt = ceil_div(i.n_subseq, 64);
+    if (nt > 0xffffffffu)
+        return HD_ERR_UNSUPPORTED;
+    const auto t_entry = std::chrono::steady_clock::now();
+    const DeviceInfo *dev = device_info();
+    const CrStreams *cs = cr_streams();
+    if (!dev || !cs)
+        return HD_ERR_DEVICE;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const uint32_t S = i.subseq_bits;
+    const uint32_t table = table_lds_bytes(s->table->k1);
+    const void *func = listed_kernel(s->table->pair, S);
+    const uint32_t reg_cap = reg_waves_per_cu(func);
+    // T_high: the largest class whose staging still leaves a quarter of the
+    // wavefront slots of a CU (8 of 32) resident -- the paper's rule (25 %
+    // occupancy) on this architecture
+    uint32_t t_high = 1;
+    for (uint32_t c = 1; c <= kCrMaxClasses - 1; ++c) {
+        uint32_t waves = 0;
+        occupancy_wpg(table, wave_area_bytes(S, cr_stage(S, c)), dev, &waves, reg_cap, func);
+        if (waves >= kMaxWavesPerCu / 4)
+            t_high = c;
+    }
+    const CrWs w = cr_ws(workspace, nt);
+    CrArgs ca;
+    ca.chunk_off = s->chunk_offsets;
+    ca.ntiles = nt;
+    ca.M = i.n_chunks;
+    ca.n = i.n_symbols;
+    ca.B = i.n_bits;
+    ca.S = S;
+    ca.Cl = chunk_log2(i.chunk_subseqs);
+    ca.t_high = t_high;
+    ca.cls = w.cls;
+    ca.hist = w.hist;
+    ca.cursor = w.cursor;
+    ca.order = w.order;
+    ca.head = w.head;
+    // device: classify, histogram, key-value sort (lines 2-7 of the figure)
+    hipLaunchKernelGGL(k_cr_clear, dim3(1), dim3(64), 0, stream, ca);
+    const uint32_t g = static_cast<uint32_t>(std::max<uint64_t>(1, ceil_div(nt, 256)));
+    if (nt) {
+        hipLaunchKernelGGL(k_cr_classify, dim3(g), dim3(256), 0, stream, ca);
+        hipLaunchKernelGGL(k_cr_sort, dim3(g), dim3(256), 0, stream, ca);
+    }
+    // host: the histogram comes back, its prefix sum gives each class's
+    // first position in the sorted tile list
+    uint32_t hist[kCrMaxClasses] = {0};
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(hist, w.hist, sizeof(hist), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return HD_ERR_DEVICE;
+    uint32_t start[kCrMaxClasses];
+    uint32_t acc = 0;
+    for (uint32_t c = 0; c < kCrMaxClasses; ++c) {
+        start[c] = acc;
+        acc += hist[c];
+    }
+    if (acc != nt)
+        return HD_ERR_DEVICE;
+    if (report) {
+        std::memset(report, 0, sizeof(*report));
+        report->t_high = t_high;
+        report->classify_us =
+            std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t_entry).count();
+    }
+    // one decode launch per non-empty class, each with its class's staging,
+    // on its own stream; the caller's stream waits for all of them
+    for (uint32_t c = 0; c <= t_high; ++c) {
+        if (!hist[c])
+            continue;
+        hd_tune tune{0, cr_stage(S, std::min(c + 1, t_high)), 0, 0};
+        Plan p;
+        st = make_plan(s, &tune, &p);
+        if (st != HD_OK)
+            return st;
+        GapArgs a;
+        a.sd.words = s->words;
+        a.sd.gap = s->gap;
+        a.sd.chunk_off = s->chunk_offsets;
+        a.sd.out = out;
+        a.sd.n = i.n_symbols;
+        a.sd.B = i.n_bits;
+        a.sd.K = i.n_subseq;
+        a.sd.M = i.n_chunks;
+        a.sd.n_words = i.n_words;
+        a.sd.S = S;
+        a.sd.last_bits = static_cast<uint32_t>(i.n_bits - (i.n_subseq - 1) * S);
+        a.sd.Cl = chunk_log2(i.chunk_subseqs);
+        a.sd.stage = p.stage;
+        a.head = w.head;
+        a.slots = nullptr;
+        a.own_head = 0;
+        a.direct = w.head;
+        a.direct_atomic = 1;
+        a.list = w.order + start[c];
+        a.n_list = hist[c];
+        a.tab = view_of(s->table);
+        // the plan sized the grid for every tile; this class has hist[c]
+        const uint64_t want = ceil_div(hist[c], p.wpg);
+        p.grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(want, p.grid)));
+        const bool small = S <= 32 * kSmallUnits;
+        hipStream_t cst = cs->s[c];
+        st = s->table->pair ? (small ? launch_listed<true, kSmallUnits>(a, p, cst)
+                                     : launch_listed<true, kMaxUnitsPerLane>(a, p, cst))
+                            : (small ? launch_listed<false, kSmallUnits>(a, p, cst)
+                                     : launch_listed<false, kMaxUnitsPerLane>(a, p, cst));
+        if (st != HD_OK)
+            return st;
+        if (hipEventRecord(cs->ev[c], cst) != hipSuccess || hipStreamWaitEvent(stream, cs->ev[c], 0) != hipSuccess)
+            return HD_ERR_DEVICE;
+        if (report) {
+            report->tiles[c] = hist[c];
+            report->stage_symbols[c] = p.stage;
+            report->waves_per_group[c] = p.wpg;
+            report->launches += 1;
+        }
+    }
+    return HD_OK;
 }
 
 extern "C" hd_status hd_decode_sync_points(const hd_dstream *s, const void *workspace, size_t ws_bytes,
@@ -2266,9 +2655,11 @@ extern "C" hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, u
     return HD_OK;
 }
 
-extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_streams,
-                                     uint16_t *const *outs, hd_mode m, const hd_tune *per_stream,
-                                     void *workspace, size_t ws_bytes, void *hip_stream)
+namespace {
+
+hd_status decode_batch_impl(const hd_dstream *streams, uint32_t n_streams, uint16_t *const *outs, hd_mode m,
+                            const hd_tune *per_stream, void *workspace, size_t ws_bytes, void *hip_stream,
+                            uint32_t *direct)
 {
     if (n_streams == 0)
         return HD_OK;
@@ -2416,12 +2807,31 @@ extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_strea
     a.streams = reinterpret_cast<const BatchStreamDev *>(ws + L.desc);
     a.n_streams = n_streams;
     a.n_items = items;
-    a.status = status;
+    a.status = direct ? direct : status;
+    a.direct = direct ? 1u : 0u;
     a.S_alloc = S_alloc;
     a.stage_alloc = stage_alloc;
     a.k1_alloc = k1_alloc;
     const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(items, uint64_t(dev->cus) * fit)));
     return launch_batch(a, formats, small, wpg, lds, grid, stream);
+}
+
+}  // namespace
+
+extern "C" hd_status hd_decode_batch(const hd_dstream *streams, uint32_t n_streams,
+                                     uint16_t *const *outs, hd_mode m, const hd_tune *per_stream,
+                                     void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    return decode_batch_impl(streams, n_streams, outs, m, per_stream, workspace, ws_bytes, hip_stream, nullptr);
+}
+
+hd_status hd::decode_batch_direct(const hd_dstream *streams, uint32_t n_streams, uint16_t *const *outs,
+                                  uint32_t *status_word, void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    if (!status_word)
+        return HD_ERR_ARG;
+    return decode_batch_impl(streams, n_streams, outs, HD_MODE_GAP, nullptr, workspace, ws_bytes, hip_stream,
+                             status_word);
 }
 
 extern "C" hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *out, void *workspace,

@@ -25,6 +25,19 @@ enum : uint32_t {
     kErrNoOutlier = 1u << 7,    // reconstruction: a code-0 position missing from the outlier list
 };
 
+// Library-internal decode calls for the serving loop (C++ linkage, not part
+// of the C ABI).  Their status goes to a caller-zeroed word, typically in
+// pinned host memory: a wavefront that met an error stores its nonzero bits
+// there with a plain store (bits of different wavefronts may overwrite one
+// another; the word is nonzero exactly when some wavefront erred), so no
+// status copy follows the decode.
+//   decode_gap_direct: hd_decode in HD_MODE_GAP without a workspace (one
+//     kernel launch);
+//   decode_batch_direct: hd_decode_batch with its status word replaced.
+hd_status decode_gap_direct(const hd_dstream *s, uint16_t *out, uint32_t *status_word, void *hip_stream);
+hd_status decode_batch_direct(const hd_dstream *streams, uint32_t n_streams, uint16_t *const *outs,
+                              uint32_t *status_word, void *workspace, size_t ws_bytes, void *hip_stream);
+
 constexpr uint32_t kLenLong = 0;     // first-level entry: codeword longer than lut_bits
 constexpr uint32_t kLenBad = 63;     // first-level entry: prefix of no codeword
 

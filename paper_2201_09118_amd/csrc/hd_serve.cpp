@@ -1,18 +1,24 @@
 // Decode server: continuous batching of decode requests under an HBM budget.
 //
-// Requests are device-resident streams (words, gap, chunk counts, table).
-// The server owns one device arena of `hbm_budget` bytes from which it
-// allocates every admitted request's output and each batch's workspace, so
-// the in-flight footprint never exceeds the budget.  A scheduler thread
-// loops: it retires batches whose completion event has fired, then admits
-// queued requests in arrival order while their output fits in the arena
-// (head-of-line: a request that does not fit waits for memory to free), and
-// launches each admitted group as one hd_decode_batch on a free HIP stream
-// (its status word comes back through an asynchronous copy to pinned memory).
-// Requests arriving while earlier batches run are admitted into new batches
-// on other streams, so their work overlaps on the device.  Outputs stay
-// allocated until the client releases them.  Destroying the server waits for
-// running batches and drops requests that were never admitted.
+// Requests are device-resident streams (words, gap array, chunk offsets,
+// table).  The server owns one device arena of `hbm_budget` bytes from which
+// it allocates every admitted request's output and each multi-request
+// batch's workspace, so the in-flight footprint never exceeds the budget.  A
+// scheduler thread loops: it retires batches whose completion event has
+// fired, then admits queued requests in arrival order while their output
+// fits in the arena (head-of-line: a request that does not fit waits for
+// memory to free), and launches each admitted group on a free HIP stream --
+// a lone request as the one-launch gap-mode decode, several as one batched
+// launch -- outside the lock, so submit, poll and release never wait for a
+// launch.  Each stream slot's status word lives in pinned host memory: the
+// host zeroes it before the launch and the kernels store nonzero error bits
+// into it, so no copy follows the decode.  While batches run (and for a short
+// idle window) the scheduler polls their events instead of sleeping; after
+// that it blocks until a submit or release.  Requests arriving while earlier
+// batches run are admitted into new batches on other streams, so their work
+// overlaps on the device.  Outputs stay allocated until the client releases
+// them.  Destroying the server waits for running batches and drops requests
+// that were never admitted.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +35,7 @@
 #include <vector>
 
 #include "hd.h"
+#include "hd_internal.h"
 
 namespace {
 
@@ -113,10 +120,19 @@ struct Request {
 
 struct Batch {
     std::vector<uint64_t> ids;
-    size_t ws_off = 0;
+    std::vector<hd_dstream> ds;          // copies taken under the lock, launched outside it
+    std::vector<uint16_t *> outs;
+    size_t ws_off = 0, ws_bytes = 0;     // a batch workspace (several requests only)
+    bool has_ws = false;
     int slot = -1;
     hipEvent_t done = nullptr;
+    hd_status launch_status = HD_OK;
 };
+
+// Busy-poll window of an idle scheduler before it blocks on the condition
+// variable (a blocked thread takes a futex wake-up, tens of microseconds, to
+// see the next submit).
+constexpr auto kIdleSpin = std::chrono::milliseconds(50);
 
 }  // namespace
 
@@ -128,34 +144,42 @@ struct hd_server {
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     std::vector<bool> slot_busy;
-    uint32_t *status_host = nullptr;       // pinned, one status word per slot
+    // pinned, one status word per stream slot: zeroed by the host before a
+    // launch, written by the decode kernels (no copy after the decode)
+    volatile uint32_t *status_host = nullptr;
 
     std::mutex mu;
     std::condition_variable cv;
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, Request> reqs;
     std::deque<uint64_t> done_q;
-    std::vector<Batch> running;
+    std::vector<Batch> running;          // touched by the scheduler thread only
     uint64_t next_id = 1;
-    bool stop = false;
+    std::atomic<bool> stop{false};
+    std::atomic<uint64_t> epoch{0};      // bumped by submit and release (under mu)
     std::thread worker;
     uint64_t n_batches = 0, n_done = 0, peak_used = 0;
 
     void loop();
     void retire_locked();
-    void launch_locked();
+    void admit_locked(std::vector<Batch> &out);
+    void launch(Batch &b);
+    void finish_locked(Batch &b);
+    void wait_for_change(uint64_t seen, Clock::time_point idle_since);
 };
 
 void hd_server::retire_locked()
 {
     for (size_t b = 0; b < running.size();) {
         Batch &bt = running[b];
-        if (hipEventQuery(bt.done) != hipSuccess) {
+        const hipError_t q = hipEventQuery(bt.done);
+        if (q == hipErrorNotReady) {
             ++b;
             continue;
         }
+        // completed, or the device reported an error for this stream
         const double t = now_s();
-        const hd_status st = status_host[bt.slot] ? HD_ERR_CORRUPT : HD_OK;
+        const hd_status st = q != hipSuccess ? HD_ERR_DEVICE : status_host[bt.slot] ? HD_ERR_CORRUPT : HD_OK;
         for (uint64_t id : bt.ids) {
             Request &r = reqs[id];
             r.state = ReqState::Done;
@@ -164,13 +188,17 @@ void hd_server::retire_locked()
             done_q.push_back(id);
             ++n_done;
         }
-        arena->release(bt.ws_off);
+        if (bt.has_ws)
+            arena->release(bt.ws_off);
         slot_busy[bt.slot] = false;
         running.erase(running.begin() + b);
     }
 }
 
-void hd_server::launch_locked()
+// Admits queued requests in arrival order into batches, one per free stream
+// slot: outputs (and, for several requests, the batch workspace) come from
+// the arena; a request that does not fit waits at the head of the queue.
+void hd_server::admit_locked(std::vector<Batch> &out)
 {
     for (;;) {
         if (queue.empty())
@@ -183,7 +211,6 @@ void hd_server::launch_locked()
             }
         if (slot < 0)
             return;
-        // admit in arrival order while outputs fit
         std::vector<uint64_t> ids;
         while (!queue.empty() && ids.size() < max_batch) {
             Request &r = reqs[queue.front()];
@@ -196,83 +223,131 @@ void hd_server::launch_locked()
         }
         if (ids.empty())
             return;
-        // the batch workspace must fit too; shrink the batch until it does
-        // (a lone request always fits an idle arena: submit checked it)
-        std::vector<hd_dstream> ds;
-        std::vector<uint16_t *> outs;
-        size_t wsb = 0, ws_off = 0;
+        Batch bt;
+        // several requests share one batched launch and its workspace; shrink
+        // the batch until the workspace fits (one request needs none)
         for (;;) {
-            ds.resize(ids.size());
-            outs.resize(ids.size());
+            bt.ds.resize(ids.size());
+            bt.outs.resize(ids.size());
             for (size_t i = 0; i < ids.size(); ++i) {
-                ds[i] = reqs[ids[i]].s;
-                outs[i] = reinterpret_cast<uint16_t *>(static_cast<char *>(base) + reqs[ids[i]].out_off);
+                bt.ds[i] = reqs[ids[i]].s;
+                bt.outs[i] = reinterpret_cast<uint16_t *>(static_cast<char *>(base) + reqs[ids[i]].out_off);
             }
-            if (hd_decode_batch_workspace_size(ds.data(), static_cast<uint32_t>(ds.size()), HD_MODE_GAP, &wsb) ==
-                    HD_OK &&
-                arena->alloc(wsb, &ws_off))
+            if (ids.size() == 1)
                 break;
+            size_t wsb = 0;
+            if (hd_decode_batch_workspace_size(bt.ds.data(), static_cast<uint32_t>(bt.ds.size()), HD_MODE_GAP,
+                                               &wsb) == HD_OK &&
+                arena->alloc(wsb, &bt.ws_off)) {
+                bt.ws_bytes = wsb;
+                bt.has_ws = true;
+                break;
+            }
             arena->release(reqs[ids.back()].out_off);
             queue.push_front(ids.back());
             ids.pop_back();
-            if (ids.empty())
-                return;
-        }
-        hd_status st = hd_decode_batch(ds.data(), static_cast<uint32_t>(ds.size()), outs.data(), HD_MODE_GAP,
-                                       nullptr, static_cast<char *>(base) + ws_off, wsb, streams[slot]);
-        // the batch's status word travels to pinned memory behind the decode
-        if (st == HD_OK && (hipMemcpyAsync(&status_host[slot], static_cast<char *>(base) + ws_off, sizeof(uint32_t),
-                                           hipMemcpyDeviceToHost, streams[slot]) != hipSuccess ||
-                            hipEventRecord(events[slot], streams[slot]) != hipSuccess)) {
-            (void)hipStreamSynchronize(streams[slot]);    // the decode may still use the workspace
-            st = HD_ERR_DEVICE;
         }
         const double t = now_s();
-        if (st != HD_OK) {
-            for (uint64_t id : ids) {
-                Request &r = reqs[id];
-                r.state = ReqState::Done;
-                r.status = st;
-                r.t_start = r.t_done = t;
-                done_q.push_back(id);
-                ++n_done;
-            }
-            arena->release(ws_off);
-            continue;
-        }
-        Batch bt;
-        bt.ids = ids;
-        bt.ws_off = ws_off;
-        bt.slot = slot;
-        bt.done = events[slot];
         for (uint64_t id : ids) {
             reqs[id].state = ReqState::Running;
             reqs[id].t_start = t;
         }
+        bt.ids = std::move(ids);
+        bt.slot = slot;
+        bt.done = events[slot];
         slot_busy[slot] = true;
-        running.push_back(bt);
-        ++n_batches;
         peak_used = std::max<uint64_t>(peak_used, arena->used());
+        out.push_back(std::move(bt));
+    }
+}
+
+// Enqueues one batch on its stream slot (outside the lock): a single request
+// takes the one-launch gap-mode decode, several take one batched launch.
+void hd_server::launch(Batch &bt)
+{
+    status_host[bt.slot] = 0;
+    hipStream_t st = streams[bt.slot];
+    uint32_t *sw = const_cast<uint32_t *>(&status_host[bt.slot]);
+    hd_status r = bt.ds.size() == 1
+                      ? hd::decode_gap_direct(&bt.ds[0], bt.outs[0], sw, st)
+                      : hd::decode_batch_direct(bt.ds.data(), static_cast<uint32_t>(bt.ds.size()), bt.outs.data(),
+                                                sw, static_cast<char *>(base) + bt.ws_off, bt.ws_bytes, st);
+    if (r == HD_OK && hipEventRecord(bt.done, st) != hipSuccess) {
+        (void)hipStreamSynchronize(st);      // the decode may still use the workspace
+        r = HD_ERR_DEVICE;
+    }
+    bt.launch_status = r;
+}
+
+void hd_server::finish_locked(Batch &bt)
+{
+    if (bt.launch_status == HD_OK) {
+        running.push_back(std::move(bt));
+        ++n_batches;
+        return;
+    }
+    const double t = now_s();
+    for (uint64_t id : bt.ids) {
+        Request &r = reqs[id];
+        r.state = ReqState::Done;
+        r.status = bt.launch_status;
+        r.t_done = t;
+        done_q.push_back(id);
+        ++n_done;
+    }
+    if (bt.has_ws)
+        arena->release(bt.ws_off);
+    slot_busy[bt.slot] = false;
+}
+
+// Returns once something may have changed: a submit or release (epoch), a
+// running batch's event, or stop.  Polls while batches run or for a short
+// idle window, then blocks on the condition variable.
+void hd_server::wait_for_change(uint64_t seen, Clock::time_point idle_since)
+{
+    for (;;) {
+        if (stop.load(std::memory_order_acquire) || epoch.load(std::memory_order_acquire) != seen)
+            return;
+        for (const Batch &b : running)
+            if (hipEventQuery(b.done) != hipErrorNotReady)
+                return;
+        if (running.empty() && Clock::now() - idle_since > kIdleSpin) {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return stop.load() || epoch.load() != seen; });
+            return;
+        }
+        std::this_thread::yield();
     }
 }
 
 void hd_server::loop()
 {
     (void)hipSetDevice(device);
+    Clock::time_point idle_since = Clock::now();
     std::unique_lock<std::mutex> lk(mu);
-    while (!stop || !running.empty()) {
+    for (;;) {
         retire_locked();
-        if (!stop)
-            launch_locked();
-        if (stop && running.empty())
+        if (stop.load() && running.empty())
             break;
-        if (running.empty() && queue.empty())
-            cv.wait_for(lk, std::chrono::milliseconds(5));
-        else {
-            lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(5));
+        std::vector<Batch> ls;
+        if (!stop.load())
+            admit_locked(ls);
+        if (!ls.empty()) {
+            lk.unlock();                     // submit, poll and release go on meanwhile
+            for (Batch &b : ls)
+                launch(b);
             lk.lock();
+            for (Batch &b : ls)
+                finish_locked(b);
+            idle_since = Clock::now();
+            continue;
         }
+        if (!running.empty())
+            idle_since = Clock::now();
+        const uint64_t seen = epoch.load();
+        lk.unlock();
+        wait_for_change(seen, idle_since);
+        lk.lock();
     }
 }
 
@@ -295,8 +370,8 @@ extern "C" hd_status hd_server_create(size_t hbm_budget, uint32_t n_hip_streams,
         return HD_ERR_NOMEM;
     }
     s->arena = new Arena(hbm_budget);
-    if (hipHostMalloc(reinterpret_cast<void **>(&s->status_host), sizeof(uint32_t) * n_hip_streams,
-                      hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(const_cast<void **>(reinterpret_cast<volatile void **>(&s->status_host)),
+                      sizeof(uint32_t) * n_hip_streams, hipHostMallocDefault) != hipSuccess) {
         (void)hipFree(s->base);
         delete s->arena;
         delete s;
@@ -311,7 +386,7 @@ extern "C" hd_status hd_server_create(size_t hbm_budget, uint32_t n_hip_streams,
                 (void)hipStreamDestroy(x);
             for (auto x : s->events)
                 (void)hipEventDestroy(x);
-            (void)hipHostFree(s->status_host);
+            (void)hipHostFree(const_cast<uint32_t *>(s->status_host));
             (void)hipFree(s->base);
             delete s->arena;
             delete s;
@@ -332,7 +407,7 @@ extern "C" void hd_server_destroy(hd_server *s)
         return;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        s->stop = true;
+        s->stop.store(true);
     }
     s->cv.notify_all();
     if (s->worker.joinable())
@@ -343,7 +418,7 @@ extern "C" void hd_server_destroy(hd_server *s)
     }
     for (auto ev : s->events)
         (void)hipEventDestroy(ev);
-    (void)hipHostFree(s->status_host);
+    (void)hipHostFree(const_cast<uint32_t *>(s->status_host));
     (void)hipFree(s->base);
     delete s->arena;
     delete s;
@@ -368,6 +443,7 @@ extern "C" hd_status hd_server_submit(hd_server *s, const hd_dstream *stream, ui
     s->reqs.emplace(r.id, r);
     s->queue.push_back(r.id);
     *request_id = r.id;
+    s->epoch.fetch_add(1, std::memory_order_release);
     s->cv.notify_all();
     return HD_OK;
 }
@@ -417,6 +493,7 @@ extern "C" hd_status hd_server_release(hd_server *s, uint64_t id)
         return HD_ERR_ARG;
     s->arena->release(it->second.out_off);
     s->reqs.erase(it);
+    s->epoch.fetch_add(1, std::memory_order_release);
     s->cv.notify_all();
     return HD_OK;
 }

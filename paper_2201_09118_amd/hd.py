@@ -38,6 +38,8 @@ SIGNATURES = {
     "hd_decode_batch_workspace_size": (C.c_int, [_vp, _u32, C.c_int, C.POINTER(_sz)]),
     "hd_decode_batch": (C.c_int, [_vp, _u32, _vp, C.c_int, _vp, _vp, _sz, _vp]),
     "hd_autotune": (C.c_int, [_vp, C.c_int, _vp, _vp, _sz, _vp, _vp, _vp]),
+    "hd_decode_cr_classes_workspace_size": (C.c_int, [_vp, C.POINTER(_sz)]),
+    "hd_decode_cr_classes": (C.c_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "hd_decode_status": (C.c_int, [_vp, _vp]),
     "hd_decode_status_bits": (_u32, [_vp, _vp]),
     "hd_lorenzo_workspace_size": (_sz, [_u32, _u32, _u32]),
@@ -81,6 +83,12 @@ class StreamInfo(C.Structure):
 class Tune(C.Structure):
     _fields_ = [("waves_per_group", C.c_uint32), ("stage_symbols", C.c_uint32),
                 ("groups_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class CrClasses(C.Structure):
+    _fields_ = [("t_high", C.c_uint32), ("launches", C.c_uint32), ("classify_us", C.c_double),
+                ("tiles", C.c_uint32 * 17),
+                ("stage_symbols", C.c_uint32 * 17), ("waves_per_group", C.c_uint32 * 17)]
 
 
 class DStream(C.Structure):
@@ -332,6 +340,24 @@ def autotune(ds: DeviceStream, out, workspace=None, mode: int = MODE_GAP, stream
     _check(lib().hd_autotune(C.byref(d), mode, _dev_ptr(out), _dev_ptr(workspace), workspace.numel(),
                              _stream_handle(stream), C.byref(best), C.byref(ms)), "hd_autotune")
     return best, float(ms.value)
+
+
+def decode_cr_classes(ds: DeviceStream, out, workspace=None, stream=None):
+    """hd_decode_cr_classes (the paper's Algorithm 2 as an ablation); returns
+    (workspace, report dict)."""
+    d = ds.as_c()
+    if workspace is None:
+        n = C.c_size_t()
+        _check(lib().hd_decode_cr_classes_workspace_size(C.byref(d), C.byref(n)),
+               "hd_decode_cr_classes_workspace_size")
+        workspace = alloc_workspace(int(n.value), out.device)
+    rep = CrClasses()
+    _check(lib().hd_decode_cr_classes(C.byref(d), _dev_ptr(out), _dev_ptr(workspace), workspace.numel(),
+                                      _stream_handle(stream), C.byref(rep)), "hd_decode_cr_classes")
+    used = [c for c in range(17) if rep.tiles[c]]
+    return workspace, {"t_high": rep.t_high, "launches": rep.launches, "classify_us": rep.classify_us,
+                       "classes": {c + 1: {"tiles": rep.tiles[c], "stage_symbols": rep.stage_symbols[c],
+                                           "waves_per_group": rep.waves_per_group[c]} for c in used}}
 
 
 def histogram(syms, A: int, hist=None, stream=None):
