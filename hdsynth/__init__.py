@@ -2,7 +2,8 @@
 
 This module only draws input symbols. It holds none of the coding arithmetic
 (no histograms of codes, no code lengths, no bit packing): both the CPU oracle
-and the GPU library take its output as plain uint16 arrays.
+and the GPU library take its output as plain unsigned arrays (uint16 by
+default; uint8 and uint32 for the other symbol widths).
 
 The paper evaluates on SZ quantization codes of eight scientific datasets
 (Sec. V-A, Table III) that are not available here.  The generators below stand
@@ -30,6 +31,8 @@ __all__ = [
     "lorenzo_field_codes",
     "config2_symbols",
     "config2_field",
+    "config2_symbols_u8",
+    "config2_symbols_u32",
     "config3_symbols",
     "batch_stream_specs",
     "batch_stream_symbols",
@@ -42,7 +45,7 @@ def rng_for(seed: int) -> np.random.Generator:
 
 
 def two_sided_geometric(rng: np.random.Generator, n: int, r: float, A: int,
-                        centre: int | None = None) -> np.ndarray:
+                        centre: int | None = None, dtype=np.uint16) -> np.ndarray:
     """x = centre + (G1 - G2), G ~ Geometric on {0,1,...} with P(G=g) ∝ r^g.
 
     The difference of two i.i.d. geometrics has P(d = k) ∝ r^|k| exactly.
@@ -55,7 +58,8 @@ def two_sided_geometric(rng: np.random.Generator, n: int, r: float, A: int,
     x += rng.geometric(p, n).astype(np.int64) - 1
     x -= rng.geometric(p, n).astype(np.int64) - 1
     x[(x < 0) | (x >= A)] = 0
-    return x.astype(np.uint16)
+    assert A - 1 <= np.iinfo(dtype).max, "alphabet does not fit the symbol type"
+    return x.astype(dtype)
 
 
 def config1_symbols(n: int = 1 << 20, seed: int = 1) -> np.ndarray:
@@ -113,7 +117,7 @@ class LorenzoField:
 
 def lorenzo_field(shape=(512, 512, 512), seed: int = 2, n_waves: int = 16,
                   noise_sigma: float = 1e-3, eb: float = 1e-4, radius: int = 512,
-                  keep_field: bool = False) -> LorenzoField:
+                  keep_field: bool = False, dtype=np.uint16) -> LorenzoField:
     """SZ-style quantization codes of a seeded smooth float32 field.
 
     field = n_waves random plane sinusoids + N(0, noise_sigma^2), float32.
@@ -122,7 +126,9 @@ def lorenzo_field(shape=(512, 512, 512), seed: int = 2, n_waves: int = 16,
     code = r + radius when 0 <= r + radius < 2 radius, else 0.  Every code-0
     position (out-of-range residuals, and r = -radius) goes to the outlier
     list with its true residual.  Flattened in C order (last axis fastest).
+    Codes are returned as `dtype`, which must hold 2 radius - 1.
     """
+    assert 2 * radius - 1 <= np.iinfo(dtype).max, "radius does not fit the code type"
     import torch
 
     rng = rng_for(seed)
@@ -145,7 +151,7 @@ def lorenzo_field(shape=(512, 512, 512), seed: int = 2, n_waves: int = 16,
         q = d
     code = q + radius
     code[(code < 0) | (code >= 2 * radius)] = 0
-    codes = code.to(torch.int32).numpy().astype(np.uint16).reshape(-1)
+    codes = code.to(torch.int32).numpy().astype(dtype).reshape(-1)
     idx = np.flatnonzero(codes == 0).astype(np.uint64)
     val = q.reshape(-1).numpy()[idx.astype(np.int64)].astype(np.int32)
     return LorenzoField(tuple(int(v) for v in shape), float(eb), int(radius), codes, idx, val, f)
@@ -166,6 +172,20 @@ def config2_symbols(seed: int = 2) -> np.ndarray:
 def config2_field(seed: int = 2, keep_field: bool = False) -> LorenzoField:
     """The 512^3 field behind config2_symbols, with its outliers (eb 1e-4, radius 512)."""
     return lorenzo_field((512, 512, 512), seed=seed, keep_field=keep_field)
+
+
+def config2_symbols_u8(seed: int = 2) -> np.ndarray:
+    """The 512^3 field of config2_symbols quantized into one-byte codes
+    (radius 128, A = 256), like the 8-bit symbols of the decoders the paper
+    starts from (its single-byte baseline trims codes to one byte)."""
+    return lorenzo_field((512, 512, 512), seed=seed, radius=128, dtype=np.uint8).codes
+
+
+def config2_symbols_u32(seed: int = 2) -> np.ndarray:
+    """The same field at a 100x tighter bound (eb 1e-6) with radius 2^17
+    (A = 2^18): codes wider than 16 bits, as tight double-precision bounds
+    need; residual spread about 1400 bins."""
+    return lorenzo_field((512, 512, 512), seed=seed, eb=1e-6, radius=1 << 17, dtype=np.uint32).codes
 
 
 def config3_symbols(n: int = 280_000_000, seed: int = 3, A: int = 4096,

@@ -1,4 +1,5 @@
-"""CPU oracle for canonical-Huffman coding of uint16 quantization codes.
+"""CPU oracle for canonical-Huffman coding of quantization codes (uint16
+symbols, and uint8 / uint32 symbols through the width-generic routines).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg are the only callers.  The product library never imports,
@@ -47,6 +48,9 @@ def lib():
         p = C.c_void_p
         u32, u64 = C.c_uint32, C.c_uint64
         L.hdref_histogram.argtypes = [p, u64, u32, p]
+        L.hdref_histogram_w.argtypes = [p, u32, u64, u32, p]
+        L.hdref_encode_w.argtypes = [p, u32, u64, p, p, u32, u32, u32, p, u64, p, u64, p, u64, p]
+        L.hdref_decode_w.argtypes = [p, u64, u64, u64, p, p, u32, p, u32]
         L.hdref_code_lengths.argtypes = [p, u32, u32, p]
         L.hdref_canonical_codes.argtypes = [p, u32, p]
         L.hdref_encode.argtypes = [p, u64, p, p, u32, u32, u32, p, u64, p, u64, p, u64, p]
@@ -56,7 +60,8 @@ def lib():
         L.hdref_selfsync.argtypes = [p, u64, u64, u64, p, p, u32, u32, p, p, p]
         L.hdref_gap_backward.argtypes = [p, u64, u64, u64, p, p, u32, u32, p, p]
         for f in ("hdref_histogram", "hdref_code_lengths", "hdref_canonical_codes", "hdref_encode",
-                  "hdref_decode", "hdref_decode_prefix", "hdref_selfsync", "hdref_gap_backward"):
+                  "hdref_decode", "hdref_decode_prefix", "hdref_selfsync", "hdref_gap_backward",
+                  "hdref_histogram_w", "hdref_encode_w", "hdref_decode_w"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -77,10 +82,24 @@ def _check(rc, what):
         raise OracleError(rc, what)
 
 
+_WIDTH_DTYPE = {1: np.uint8, 2: np.uint16, 4: np.uint32}
+
+
+def _symbols(x: np.ndarray):
+    """(contiguous symbol array, width in bytes): uint8 and uint32 arrays keep
+    their width, anything else is taken as uint16."""
+    x = np.asarray(x)
+    if x.dtype == np.uint8:
+        return np.ascontiguousarray(x), 1
+    if x.dtype == np.uint32:
+        return np.ascontiguousarray(x), 4
+    return np.ascontiguousarray(x, dtype=np.uint16), 2
+
+
 def histogram(x: np.ndarray, A: int) -> np.ndarray:
-    x = np.ascontiguousarray(x, dtype=np.uint16)
+    x, w = _symbols(x)
     cnt = np.zeros(A, dtype=np.uint64)
-    _check(lib().hdref_histogram(_ptr(x), x.size, A, _ptr(cnt)), "histogram")
+    _check(lib().hdref_histogram_w(_ptr(x), w, x.size, A, _ptr(cnt)), "histogram")
     return cnt
 
 
@@ -126,30 +145,33 @@ class Encoded:
 
 
 def encode(x: np.ndarray, lengths: np.ndarray, codes: np.ndarray, S: int = 128, C: int = 32) -> Encoded:
-    x = np.ascontiguousarray(x, dtype=np.uint16)
+    """Encodes x (uint8 / uint32 arrays at their width, anything else as uint16)."""
+    x, wid = _symbols(x)
     lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
     codes = np.ascontiguousarray(codes, dtype=np.uint32)
     A = lengths.size
     info = np.zeros(4, dtype=np.uint64)
     L = lib()
-    _check(L.hdref_encode(_ptr(x), x.size, _ptr(lengths), _ptr(codes), A, S, C,
-                          None, 0, None, 0, None, 0, _ptr(info)), "encode(size)")
+    _check(L.hdref_encode_w(_ptr(x), wid, x.size, _ptr(lengths), _ptr(codes), A, S, C,
+                            None, 0, None, 0, None, 0, _ptr(info)), "encode(size)")
     B, NW, K, M = (int(v) for v in info)
     words = np.zeros(NW, dtype=np.uint32)
     gap = np.zeros(K, dtype=np.uint8)
     cc = np.zeros(M, dtype=np.uint32)
-    _check(L.hdref_encode(_ptr(x), x.size, _ptr(lengths), _ptr(codes), A, S, C,
-                          _ptr(words), NW, _ptr(gap), K, _ptr(cc), M, _ptr(info)), "encode")
+    _check(L.hdref_encode_w(_ptr(x), wid, x.size, _ptr(lengths), _ptr(codes), A, S, C,
+                            _ptr(words), NW, _ptr(gap), K, _ptr(cc), M, _ptr(info)), "encode")
     return Encoded(words, gap, cc, x.size, B, S, C)
 
 
-def decode(words: np.ndarray, n_bits: int, n: int, lengths: np.ndarray, codes: np.ndarray) -> np.ndarray:
+def decode(words: np.ndarray, n_bits: int, n: int, lengths: np.ndarray, codes: np.ndarray,
+           width: int = 2) -> np.ndarray:
+    """Bit-serial decode of n symbols into an unsigned array of `width` bytes (1, 2 or 4)."""
     words = np.ascontiguousarray(words, dtype=np.uint32)
     lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
     codes = np.ascontiguousarray(codes, dtype=np.uint32)
-    out = np.zeros(n, dtype=np.uint16)
-    _check(lib().hdref_decode(_ptr(words), words.size, n_bits, n, _ptr(lengths), _ptr(codes),
-                              lengths.size, _ptr(out)), "decode")
+    out = np.zeros(n, dtype=_WIDTH_DTYPE[width])
+    _check(lib().hdref_decode_w(_ptr(words), words.size, n_bits, n, _ptr(lengths), _ptr(codes),
+                                lengths.size, _ptr(out), width), "decode")
     return out
 
 

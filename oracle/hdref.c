@@ -1,5 +1,6 @@
 /*
- * hdref.c -- CPU ORACLE FOR CANONICAL-HUFFMAN CODING OF uint16 QUANTIZATION CODES.
+ * hdref.c -- CPU ORACLE FOR CANONICAL-HUFFMAN CODING OF QUANTIZATION CODES
+ * (uint16 symbols; the _w entry points also take uint8 and uint32 symbols).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
  * benchmark's CPU-baseline leg may load this file's library.  The product
@@ -65,21 +66,72 @@
 #define HDREF_ENOMEM (-5)
 
 /* ------------------------------------------------------------------------ */
+/* Symbol widths                                                             */
+/* ------------------------------------------------------------------------ */
+/*
+ * The original decoders took one-byte symbols; the paper adapts them to
+ * multi-byte quantization codes (Sec. IV) and notes that the same holds for
+ * double-precision data (Sec. V-A-3), whose codes can need a wider integer.
+ * A symbol array here holds unsigned integers of 1, 2 or 4 bytes; the
+ * alphabet must fit the width: at most 2^8, 2^16 or HDREF_MAX_ALPHABET
+ * symbols.  The 16-bit entry points are the width-2 case.
+ */
+#define HDREF_MAX_ALPHABET (1u << 24)
+
+static int width_fits(uint32_t width, uint32_t A)
+{
+    if (A == 0)
+        return 0;
+    if (width == 1)
+        return A <= 256u;
+    if (width == 2)
+        return A <= 65536u;
+    if (width == 4)
+        return A <= HDREF_MAX_ALPHABET;
+    return 0;
+}
+
+static uint32_t sym_get(const void *x, uint32_t width, uint64_t i)
+{
+    if (width == 1)
+        return ((const uint8_t *)x)[i];
+    if (width == 2)
+        return ((const uint16_t *)x)[i];
+    return ((const uint32_t *)x)[i];
+}
+
+static void sym_set(void *out, uint32_t width, uint64_t i, uint32_t v)
+{
+    if (width == 1)
+        ((uint8_t *)out)[i] = (uint8_t)v;
+    else if (width == 2)
+        ((uint16_t *)out)[i] = (uint16_t)v;
+    else
+        ((uint32_t *)out)[i] = v;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Histogram                                                                 */
 /* ------------------------------------------------------------------------ */
 
-int hdref_histogram(const uint16_t *x, uint64_t n, uint32_t A, uint64_t *cnt)
+int hdref_histogram_w(const void *x, uint32_t width, uint64_t n, uint32_t A, uint64_t *cnt)
 {
-    if (A == 0 || A > 65536 || (n > 0 && x == NULL) || cnt == NULL)
+    if (!width_fits(width, A) || (n > 0 && x == NULL) || cnt == NULL)
         return HDREF_EARG;
     for (uint32_t s = 0; s < A; ++s)
         cnt[s] = 0;
     for (uint64_t i = 0; i < n; ++i) {
-        if (x[i] >= A)
+        uint32_t v = sym_get(x, width, i);
+        if (v >= A)
             return HDREF_ESYMBOL;
-        cnt[x[i]] += 1;
+        cnt[v] += 1;
     }
     return HDREF_OK;
+}
+
+int hdref_histogram(const uint16_t *x, uint64_t n, uint32_t A, uint64_t *cnt)
+{
+    return hdref_histogram_w(x, 2, n, A, cnt);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -119,7 +171,7 @@ static int pm_leaf_cmp(const void *pa, const void *pb)
 
 int hdref_code_lengths(const uint64_t *cnt, uint32_t A, uint32_t L, uint8_t *len)
 {
-    if (cnt == NULL || len == NULL || A == 0 || A > 65536 || L < 1 || L > 32)
+    if (cnt == NULL || len == NULL || A == 0 || A > HDREF_MAX_ALPHABET || L < 1 || L > 32)
         return HDREF_EARG;
     uint32_t m = 0;
     for (uint32_t s = 0; s < A; ++s) {
@@ -259,7 +311,7 @@ static int cc_cmp(const void *pa, const void *pb)
  * Codes are right-aligned in uint32.  Unused symbols get code 0. */
 int hdref_canonical_codes(const uint8_t *len, uint32_t A, uint32_t *code)
 {
-    if (len == NULL || code == NULL || A == 0 || A > 65536)
+    if (len == NULL || code == NULL || A == 0 || A > HDREF_MAX_ALPHABET)
         return HDREF_EARG;
     cc_item *it = (cc_item *)malloc(sizeof(cc_item) * A);
     if (!it)
@@ -312,20 +364,21 @@ static unsigned get_bit(const uint32_t *words, uint64_t pos)
  * info[2] = K (subsequences), info[3] = M (chunks).
  * With words == NULL only info is filled (size query).
  */
-int hdref_encode(const uint16_t *x, uint64_t n, const uint8_t *len, const uint32_t *code,
-                 uint32_t A, uint32_t S, uint32_t C,
-                 uint32_t *words, uint64_t words_cap, uint8_t *gap, uint64_t gap_cap,
-                 uint32_t *chunk_counts, uint64_t chunk_cap, uint64_t *info)
+int hdref_encode_w(const void *x, uint32_t width, uint64_t n, const uint8_t *len, const uint32_t *code,
+                   uint32_t A, uint32_t S, uint32_t C,
+                   uint32_t *words, uint64_t words_cap, uint8_t *gap, uint64_t gap_cap,
+                   uint32_t *chunk_counts, uint64_t chunk_cap, uint64_t *info)
 {
     if ((n > 0 && x == NULL) || len == NULL || code == NULL || info == NULL)
         return HDREF_EARG;
-    if (A == 0 || A > 65536 || S == 0 || C == 0)
+    if (!width_fits(width, A) || S == 0 || C == 0)
         return HDREF_EARG;
     uint64_t B = 0;
     for (uint64_t i = 0; i < n; ++i) {
-        if (x[i] >= A || len[x[i]] == 0)
+        uint32_t v = sym_get(x, width, i);
+        if (v >= A || len[v] == 0)
             return HDREF_ESYMBOL;
-        B += len[x[i]];
+        B += len[v];
     }
     uint64_t K = (B + S - 1) / S;
     uint64_t M = (K + C - 1) / C;
@@ -352,8 +405,9 @@ int hdref_encode(const uint16_t *x, uint64_t n, const uint8_t *len, const uint32
             ++kb;
         }
         chunk_counts[(pos / S) / C] += 1;
-        unsigned l = len[x[i]];
-        uint32_t cw = code[x[i]];
+        uint32_t v = sym_get(x, width, i);
+        unsigned l = len[v];
+        uint32_t cw = code[v];
         for (unsigned b = 0; b < l; ++b)            /* MSB of the codeword first */
             put_bit(words, pos + b, (cw >> (l - 1 - b)) & 1u);
         pos += l;
@@ -364,6 +418,15 @@ int hdref_encode(const uint16_t *x, uint64_t n, const uint8_t *len, const uint32
         ++kb;
     }
     return HDREF_OK;
+}
+
+int hdref_encode(const uint16_t *x, uint64_t n, const uint8_t *len, const uint32_t *code,
+                 uint32_t A, uint32_t S, uint32_t C,
+                 uint32_t *words, uint64_t words_cap, uint8_t *gap, uint64_t gap_cap,
+                 uint32_t *chunk_counts, uint64_t chunk_cap, uint64_t *info)
+{
+    return hdref_encode_w(x, 2, n, len, code, A, S, C, words, words_cap, gap, gap_cap, chunk_counts,
+                          chunk_cap, info);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -451,10 +514,10 @@ static int64_t tr_step(const tr_tree *t, const uint32_t *words, uint64_t *pos, u
 
 /* Decodes exactly n symbols from bit 0 and requires the stream to end at
  * bit B.  words must hold at least ceil(B/32) units. */
-int hdref_decode(const uint32_t *words, uint64_t n_words, uint64_t B, uint64_t n,
-                 const uint8_t *len, const uint32_t *code, uint32_t A, uint16_t *out)
+int hdref_decode_w(const uint32_t *words, uint64_t n_words, uint64_t B, uint64_t n,
+                   const uint8_t *len, const uint32_t *code, uint32_t A, void *out, uint32_t width)
 {
-    if (len == NULL || code == NULL || A == 0 || A > 65536 || (n > 0 && (out == NULL || words == NULL)))
+    if (len == NULL || code == NULL || !width_fits(width, A) || (n > 0 && (out == NULL || words == NULL)))
         return HDREF_EARG;
     if (n_words * 32 < B)
         return HDREF_EARG;
@@ -471,10 +534,16 @@ int hdref_decode(const uint32_t *words, uint64_t n_words, uint64_t B, uint64_t n
             free(t.nodes);
             return HDREF_ECORRUPT;
         }
-        out[i] = (uint16_t)s;
+        sym_set(out, width, i, (uint32_t)s);
     }
     free(t.nodes);
     return pos == B ? HDREF_OK : HDREF_ECORRUPT;
+}
+
+int hdref_decode(const uint32_t *words, uint64_t n_words, uint64_t B, uint64_t n,
+                 const uint8_t *len, const uint32_t *code, uint32_t A, uint16_t *out)
+{
+    return hdref_decode_w(words, n_words, B, n, len, code, A, out, 2);
 }
 
 /* Decodes the first n symbols without the end-of-stream check and returns the
@@ -562,7 +631,7 @@ int hdref_selfsync(const uint32_t *words, uint64_t n_words, uint64_t B, uint64_t
                    const uint8_t *len, const uint32_t *code, uint32_t A, uint32_t S,
                    uint8_t *sync_gap, uint32_t *counts, uint32_t *sync_bits)
 {
-    if (len == NULL || code == NULL || A == 0 || A > 65536 || S == 0)
+    if (len == NULL || code == NULL || A == 0 || A > HDREF_MAX_ALPHABET || S == 0)
         return HDREF_EARG;
     if (n_words * 32 < B || (B > 0 && words == NULL))
         return HDREF_EARG;
