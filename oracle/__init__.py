@@ -51,6 +51,7 @@ def lib():
         L.hdref_histogram_w.argtypes = [p, u32, u64, u32, p]
         L.hdref_encode_w.argtypes = [p, u32, u64, p, p, u32, u32, u32, p, u64, p, u64, p, u64, p]
         L.hdref_decode_w.argtypes = [p, u64, u64, u64, p, p, u32, p, u32]
+        L.hdref_decode_from_w.argtypes = [p, u64, u64, u64, u64, p, p, u32, p, u32, p]
         L.hdref_code_lengths.argtypes = [p, u32, u32, p]
         L.hdref_canonical_codes.argtypes = [p, u32, p]
         L.hdref_encode.argtypes = [p, u64, p, p, u32, u32, u32, p, u64, p, u64, p, u64, p]
@@ -61,7 +62,7 @@ def lib():
         L.hdref_gap_backward.argtypes = [p, u64, u64, u64, p, p, u32, u32, p, p]
         for f in ("hdref_histogram", "hdref_code_lengths", "hdref_canonical_codes", "hdref_encode",
                   "hdref_decode", "hdref_decode_prefix", "hdref_selfsync", "hdref_gap_backward",
-                  "hdref_histogram_w", "hdref_encode_w", "hdref_decode_w"):
+                  "hdref_histogram_w", "hdref_encode_w", "hdref_decode_w", "hdref_decode_from_w"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -188,21 +189,22 @@ def decode_prefix(words, n_bits, n, lengths, codes, out=None):
     return out, int(end[0])
 
 
-def decode_from(words, n_bits, start, n, lengths, codes, out=None):
-    """Decodes n symbols from codeword start `start` (no end check); returns (symbols, end bit)."""
+def decode_from(words, n_bits, start, n, lengths, codes, out=None, width: int = 2):
+    """Decodes n symbols from codeword start `start` (no end check) into an
+    unsigned array of `width` bytes; returns (symbols, end bit)."""
     words = np.ascontiguousarray(words, dtype=np.uint32)
     lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
     codes = np.ascontiguousarray(codes, dtype=np.uint32)
     if out is None:
-        out = np.zeros(n, dtype=np.uint16)
-    assert out.dtype == np.uint16 and out.flags.c_contiguous and out.size >= n
+        out = np.zeros(n, dtype=_WIDTH_DTYPE[width])
+    assert out.dtype == _WIDTH_DTYPE[width] and out.flags.c_contiguous and out.size >= n
     end = np.zeros(1, dtype=np.uint64)
-    _check(lib().hdref_decode_from(_ptr(words), words.size, n_bits, start, n, _ptr(lengths), _ptr(codes),
-                                   lengths.size, _ptr(out), _ptr(end)), "decode_from")
+    _check(lib().hdref_decode_from_w(_ptr(words), words.size, n_bits, start, n, _ptr(lengths), _ptr(codes),
+                                     lengths.size, _ptr(out), width, _ptr(end)), "decode_from")
     return out, int(end[0])
 
 
-def decode_chunks_parallel(words, n_bits, n, lengths, codes, gap, chunk_offsets, S, C, threads):
+def decode_chunks_parallel(words, n_bits, n, lengths, codes, gap, chunk_offsets, S, C, threads, width: int = 2):
     """The bit-serial decoder run on `threads` host threads, one contiguous
     range of chunks each, every range starting at its first subsequence's gap
     entry and writing from its first chunk's offset (chunk_offsets: uint64[M + 1]).
@@ -211,7 +213,7 @@ def decode_chunks_parallel(words, n_bits, n, lengths, codes, gap, chunk_offsets,
     words = np.ascontiguousarray(words, dtype=np.uint32)
     lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
     codes = np.ascontiguousarray(codes, dtype=np.uint32)
-    out = np.zeros(n, dtype=np.uint16)
+    out = np.zeros(n, dtype=_WIDTH_DTYPE[width])
     M = int(chunk_offsets.size) - 1
     off = np.ascontiguousarray(chunk_offsets, dtype=np.uint64)
     bounds = [M * i // threads for i in range(threads + 1)]
@@ -223,7 +225,7 @@ def decode_chunks_parallel(words, n_bits, n, lengths, codes, gap, chunk_offsets,
         k0 = c0 * C
         start = k0 * S + int(gap[k0])
         o0, o1 = int(off[c0]), int(off[c1])
-        decode_from(words, n_bits, start, o1 - o0, lengths, codes, out[o0:o1])
+        decode_from(words, n_bits, start, o1 - o0, lengths, codes, out[o0:o1], width)
 
     with ThreadPoolExecutor(threads) as ex:
         list(ex.map(run, range(threads)))

@@ -583,11 +583,11 @@ int hdref_decode_prefix(const uint32_t *words, uint64_t n_words, uint64_t B, uin
  * (start = k*S + gap[k]) and chunk counts (n), so a CPU baseline can run one
  * call per range on every host core (Sec. III-C: the gap array lets each
  * thread begin at a known codeword boundary). */
-int hdref_decode_from(const uint32_t *words, uint64_t n_words, uint64_t B, uint64_t start, uint64_t n,
-                      const uint8_t *len, const uint32_t *code, uint32_t A, uint16_t *out,
-                      uint64_t *end_pos)
+int hdref_decode_from_w(const uint32_t *words, uint64_t n_words, uint64_t B, uint64_t start, uint64_t n,
+                        const uint8_t *len, const uint32_t *code, uint32_t A, void *out, uint32_t width,
+                        uint64_t *end_pos)
 {
-    if (len == NULL || code == NULL || A == 0 || A > 65536 || (n > 0 && (out == NULL || words == NULL)))
+    if (len == NULL || code == NULL || !width_fits(width, A) || (n > 0 && (out == NULL || words == NULL)))
         return HDREF_EARG;
     if (n_words * 32 < B || start > B)
         return HDREF_EARG;
@@ -604,12 +604,19 @@ int hdref_decode_from(const uint32_t *words, uint64_t n_words, uint64_t B, uint6
             free(t.nodes);
             return HDREF_ECORRUPT;
         }
-        out[i] = (uint16_t)s;
+        sym_set(out, width, i, (uint32_t)s);
     }
     if (end_pos)
         *end_pos = pos;
     free(t.nodes);
     return HDREF_OK;
+}
+
+int hdref_decode_from(const uint32_t *words, uint64_t n_words, uint64_t B, uint64_t start, uint64_t n,
+                      const uint8_t *len, const uint32_t *code, uint32_t A, uint16_t *out,
+                      uint64_t *end_pos)
+{
+    return hdref_decode_from_w(words, n_words, B, start, n, len, code, A, out, 2, end_pos);
 }
 
 /* ------------------------------------------------------------------------ */

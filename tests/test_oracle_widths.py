@@ -109,3 +109,16 @@ def test_width_alphabet_limits():
     with pytest.raises(oracle.OracleError) as ei:
         oracle.histogram(np.array([300], np.uint32), 256)
     assert ei.value.rc == oracle.ESYMBOL
+
+
+@pytest.mark.parametrize("dt,w", [(np.uint8, 1), (np.uint32, 4)])
+def test_chunk_parallel_decode_other_widths(dt, w):
+    rng = np.random.default_rng(35)
+    A = 256 if w == 1 else 1 << 18
+    x = hdsynth.two_sided_geometric(rng, 123_457, 0.7 if w == 1 else 0.998, A, dtype=dt)
+    ln = oracle.code_lengths(oracle.histogram(x, A), 24)
+    cd = oracle.canonical_codes(ln)
+    e = oracle.encode(x, ln, cd, 128, 8)
+    got = oracle.decode_chunks_parallel(e.words, e.n_bits, x.size, ln, cd, e.gap, e.chunk_offsets, 128, 8, 5,
+                                        width=w)
+    assert got.dtype == dt and np.array_equal(got, x)
