@@ -66,6 +66,14 @@ def workload(name):
     if name == "config3":
         return dict(x=hdsynth.config3_symbols(), A=4096, L=27, S=256, C=32,
                     desc="280M discretised Gaussian sigma 40 + 0.1% outliers, A=4096, L=27, S=256, C=32")
+    if name == "config2_u8":
+        return dict(x=hdsynth.config2_symbols_u8(), A=256, L=24, S=128, C=32,
+                    desc="the config-2 field quantized into one-byte codes (radius 128), uint8 symbols, "
+                         "A=256, L=24, S=128, C=32")
+    if name == "config2_u32":
+        return dict(x=hdsynth.config2_symbols_u32(), A=1 << 18, L=24, S=128, C=32,
+                    desc="the config-2 field at eb 1e-6 with radius 2^17, uint32 symbols, A=2^18, L=24, "
+                         "S=128, C=32")
     raise ValueError(name)
 
 
@@ -86,7 +94,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["gap", "selfsync", "both"], default="both")
-    ap.add_argument("--workload", choices=["config1", "config2", "config3", "batch", "serve", "sz", "sz1d", "encode", "lds_sweep",
+    ap.add_argument("--workload", choices=["config1", "config2", "config3", "config2_u8", "config2_u32", "batch", "serve", "sz", "sz1d", "encode", "lds_sweep",
                              "cr_classes"], default="config2")
     ap.add_argument("--batch-streams", type=int, default=256)
     ap.add_argument("--batch-lo", type=int, default=1 << 16)
@@ -149,6 +157,9 @@ def main():
     w = workload(args.workload)
     x, A, L, S, Cc = w["x"], w["A"], w["L"], w["S"], w["C"]
     n = int(x.size)
+    wid = x.dtype.itemsize                     # symbol width in bytes (1, 2 or 4)
+    out_dtype = {1: torch.uint8, 2: torch.int16, 4: torch.int32}[wid]
+    np_dtype = {1: np.uint8, 2: np.uint16, 4: np.uint32}[wid]
     log(f"generated {args.workload}: n={n} in {time.time() - t0:.1f}s")
 
     t0 = time.time()
@@ -164,11 +175,11 @@ def main():
     conv = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        y = oracle.decode(hs.words, B, n, ln, cd)
+        y = oracle.decode(hs.words, B, n, ln, cd, width=wid)
         dt = time.perf_counter() - t0
         ok = bool(np.array_equal(y, x))
         del y
-        cpu = {"value": round(2.0 * n / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": round(wid * n / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"whole {args.workload} stream ({n} symbols), one pass of the bit-serial "
                          f"prefix-tree decoder on one core, {dt:.2f} s", "verified": ok}
         log(f"cpu oracle: {dt:.2f}s ({cpu['value']} GB/s), correct={ok}")
@@ -176,11 +187,12 @@ def main():
         # (each range starts at its first subsequence's gap entry)
         threads = max(1, min(args.cpu_threads, len(os.sched_getaffinity(0))))
         t0 = time.perf_counter()
-        y = oracle.decode_chunks_parallel(hs.words, B, n, ln, cd, hs.gap, hs.chunk_offsets, S, Cc, threads)
+        y = oracle.decode_chunks_parallel(hs.words, B, n, ln, cd, hs.gap, hs.chunk_offsets, S, Cc, threads,
+                                          width=wid)
         dt = time.perf_counter() - t0
         okp = bool(np.array_equal(y, x))
         del y
-        cpu["all_cores"] = {"value": round(2.0 * n / dt / 1e9, 4), "unit": "GB/s", "cores": threads,
+        cpu["all_cores"] = {"value": round(wid * n / dt / 1e9, 4), "unit": "GB/s", "cores": threads,
                             "seconds": round(dt, 3), "verified": okp,
                             "cpu": _cpu_model(), "host_cpus": os.cpu_count()}
         log(f"cpu oracle on {threads} threads: {dt:.2f}s ({cpu['all_cores']['value']} GB/s), correct={okp}")
@@ -238,7 +250,7 @@ def main():
         log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     tab = hd.Table(ln, cd, L, args.lut_bits)
     tune = hd.Tune(args.wpg, args.stage, args.groups_per_cu, 0)
-    out = torch.empty(n, dtype=torch.int16, device=dev)
+    out = torch.empty(n, dtype=out_dtype, device=dev)
     modes = ["gap", "selfsync"] if args.mode == "both" else [args.mode]
     res = {}
     for mname in modes:
@@ -246,10 +258,10 @@ def main():
         ds = hd.DeviceStream.from_host(hs, tab, device=dev, with_gap=(mname == "gap"))
         ws = hd.alloc_workspace(hd.decode_workspace_size(ds, mode, tune), dev)
         # correctness of the timed configuration against the generated symbols
-        out.fill_(-1)
+        out.fill_(-1 if wid > 1 else 255)
         hd.decode(ds, out, mode, tune, ws, stream)
         status = hd.decode_status(ws, stream)
-        got = out.cpu().numpy().view(np.uint16)
+        got = out.cpu().numpy().view(np_dtype)
         verified = bool(status == hd.OK and np.array_equal(got, x))
         del got
         log(f"{mname}: gpu verify status={status} verified={verified}")
@@ -300,12 +312,12 @@ def main():
         del scrub
         pct = lambda v, q: round(float(np.percentile(v, q)), 5) if len(v) else None
         res[mname] = dict(ms_step=ms_step, k_ms=k_avg, verified=verified,
-                          value=2.0 * n / (ms_step * 1e-3) / 1e9,
+                          value=float(wid) * n / (ms_step * 1e-3) / 1e9,
                           warm={"median_ms": pct(steps_ms, 50), "p10_ms": pct(steps_ms, 10),
                                 "p90_ms": pct(steps_ms, 90), "decode_run_median_ms": pct(k_all, 50)},
                           cold={"steps": len(cold_ms), "median_ms": pct(cold_ms, 50), "p10_ms": pct(cold_ms, 10),
                                 "p90_ms": pct(cold_ms, 90),
-                                "gbs": round(2.0 * n / (np.median(cold_ms) * 1e-3) / 1e9, 2) if cold_ms else None})
+                                "gbs": round(wid * n / (np.median(cold_ms) * 1e-3) / 1e9, 2) if cold_ms else None})
         log(f"{mname}: {ms_step:.4f} ms/step ({res[mname]['value']:.1f} GB/s), decode kernel {k_avg:.4f} ms; "
             f"warm {res[mname]['warm']}, cold {res[mname]['cold']}")
         del ds, ws
@@ -313,7 +325,7 @@ def main():
     head = res[modes[0]]
     n_words_used = K * S // 32
     # decode kernel algorithmic bytes: output + bitstream + gap array + chunk offsets
-    alg_bytes = 2 * n + 4 * n_words_used + K + 8 * (M + 1)
+    alg_bytes = wid * n + 4 * n_words_used + K + 8 * (M + 1)
     achieved = alg_bytes / (head["k_ms"] * 1e-3) / 1e9
     rec = {
         "metric": "decoded output GB/s at 134M syms (% HBM roofline); batched speedup; p50/p99",
@@ -326,7 +338,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u16",
+        "dtype": {1: "u8", 2: "u16", 4: "u32"}[wid],
         "data": "synthetic",
         "config": {"workload": args.workload, "description": w["desc"], "mode": modes[0],
                    "n_symbols": n, "n_bits": B, "mean_code_len": round(lbar, 4),
@@ -335,11 +347,11 @@ def main():
                    "tune": {"waves_per_group": args.wpg, "stage_symbols": args.stage,
                             "groups_per_cu": args.groups_per_cu}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "kernel": "k_decode_gap",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic() if args.workload == "config2" else None, "kernel": "k_decode_gap",
                      "kernel_ms": round(head["k_ms"], 5), "alg_bytes_per_launch": alg_bytes,
                      "copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
                      "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
-                     "decoded_output_gbs_kernel": round(2.0 * n / (head["k_ms"] * 1e-3) / 1e9, 2),
+                     "decoded_output_gbs_kernel": round(wid * n / (head["k_ms"] * 1e-3) / 1e9, 2),
                      # the whole call (output-index phase + decode) against the same bytes
                      "frac_call": round(alg_bytes / (head["ms_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu,
@@ -539,10 +551,12 @@ def bench_sz(args):
 
 def bench_encode(args):
     """Device encoding of the 512^3 config-2 codes (A 1024, L 24, S 128, C 32).
-    One step: device histogram, histogram to the host (8 KiB), codebook on the
-    host, codebook to the device, plan (one host wait for the total bits),
-    write.  value = input GB/s = 2 bytes x n / step time; the device kernels
-    alone (plan + write, codebook fixed) are timed with HIP events too."""
+    One step: device histogram, device codebook (hd_build_codebook_device),
+    plan (one host wait for the total bits), write: no other host round trip.
+    value = input GB/s = 2 bytes x n / step time.  Also timed: the same step
+    with the codebook built on the host (histogram to the host, codebook back),
+    the codebook kernel alone, and the device kernels alone (plan + write,
+    codebook fixed), each with HIP events."""
     import torch
     import hdsynth
     import oracle
@@ -556,16 +570,32 @@ def bench_encode(args):
     stream = torch.cuda.current_stream(dev)
     xs = torch.from_numpy(x.view(np.int16)).to(dev)
 
-    def step():
-        hist = hd.histogram(xs, A, stream=stream).cpu().numpy().astype(np.uint64)
-        ln, cd = hd.build_codebook(hist, L)
-        lnd = torch.from_numpy(ln.astype(np.uint8)).to(dev)
-        cdd = torch.from_numpy(cd.astype(np.uint32).view(np.int32)).to(dev)
-        enc, ws = hd.encode_device(xs, lnd, cdd, L, S, Cc, stream=stream)
-        return enc, ws, ln, cd, lnd, cdd
+    cb_ws = hd.alloc_workspace(int(hd.lib().hd_codebook_workspace_size(L)), dev)
+    hist_d = torch.empty(A, dtype=torch.int64, device=dev)
+    lnd = torch.empty(A, dtype=torch.uint8, device=dev)
+    cdd = torch.empty(A, dtype=torch.int32, device=dev)
 
-    enc, ws, ln, cd, lnd, cdd = step()
+    def step():
+        hd.histogram(xs, A, hist_d, stream=stream)
+        hd.build_codebook_device(hist_d, L, lnd, cdd, cb_ws, stream=stream)
+        enc, ws = hd.encode_device(xs, lnd, cdd, L, S, Cc, stream=stream)
+        return enc, ws
+
+    def step_host_codebook():
+        hist = hd.histogram(xs, A, stream=stream).cpu().numpy().astype(np.uint64)
+        ln_h, cd_h = hd.build_codebook(hist, L)
+        lnh = torch.from_numpy(ln_h.astype(np.uint8)).to(dev)
+        cdh = torch.from_numpy(cd_h.astype(np.uint32).view(np.int32)).to(dev)
+        return hd.encode_device(xs, lnh, cdh, L, S, Cc, stream=stream)
+
+    enc, ws = step()
     torch.cuda.synchronize()
+    cb_bits = hd.decode_status_bits(cb_ws, stream)
+    ln = lnd.cpu().numpy()
+    cd = cdd.cpu().numpy().view(np.uint32)
+    ln_host, cd_host = hd.build_codebook(np.bincount(x, minlength=A).astype(np.uint64), L)
+    book_ok = cb_bits == 0 and np.array_equal(ln, ln_host) and np.array_equal(cd, cd_host)
+    log(f"device codebook equals the host builder's: {book_ok}")
     # the oracle packs with the same codebook (the codebook is an input of
     # the encoder); its histogram + codebook + packing is the CPU baseline
     t0 = time.perf_counter()
@@ -575,7 +605,7 @@ def bench_encode(args):
     cpu = None if args.no_cpu_baseline else {
         "value": round(2.0 * n / t_cpu / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
         "sample": f"whole stream ({n} symbols): oracle histogram + codebook + encode, one core, {t_cpu:.2f} s"}
-    ok = (hd.decode_status_bits(ws) == 0 and enc.n_bits == e_ref.n_bits and
+    ok = (book_ok and hd.decode_status_bits(ws) == 0 and enc.n_bits == e_ref.n_bits and
           np.array_equal(enc.words.cpu().numpy().view(np.uint32), e_ref.words) and
           np.array_equal(enc.gap.cpu().numpy(), e_ref.gap) and
           np.array_equal(enc.chunk_offsets.cpu().numpy().view(np.uint64), e_ref.chunk_offsets))
@@ -588,6 +618,23 @@ def bench_encode(args):
         step()
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    for _ in range(args.warmup):
+        step_host_codebook()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_host_codebook()
+    torch.cuda.synchronize()
+    ms_step_host = (time.perf_counter() - t0) * 1e3 / args.steps
+    # the codebook kernel alone
+    evc = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in evc:
+        a.record(stream)
+        hd.build_codebook_device(hist_d, L, lnd, cdd, cb_ws, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    cb_ms = float(np.median([a.elapsed_time(b) for a, b in evc]))
+    log(f"encode step {ms_step:.4f} ms (device codebook {cb_ms:.4f} ms), with the host codebook {ms_step_host:.4f} ms")
     # device kernels alone: plan + write into preallocated outputs
     lay = hd.Layout(S, Cc)
     K = (enc.n_bits + S - 1) // S
@@ -622,7 +669,11 @@ def bench_encode(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
         "config": {"workload": "encode", "n_symbols": n, "alphabet": A, "max_len": L, "subseq_bits": S,
                    "chunk_subseqs": Cc, "n_bits": enc.n_bits,
-                   "step": "histogram + host codebook + plan + host wait + write"},
+                   "step": "histogram + device codebook + plan + host wait + write"},
+        "codebook_kernel_ms": round(cb_ms, 5),
+        "with_host_codebook": {"ms_per_step": round(ms_step_host, 5),
+                               "value": round(2.0 * n / (ms_step_host * 1e-3) / 1e9, 2),
+                               "step": "histogram + D2H + host codebook + H2D + plan + host wait + write"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "hd_encode_plan + hd_encode_write", "kernel_ms": round(k_ms, 5),

@@ -35,7 +35,17 @@
  * Codebooks are canonical (codes of one length are consecutive integers in
  * symbol order, each length's first code continuing the previous length's);
  * lengths[s] = 0 marks a symbol without a codeword.  Codes are right-aligned
- * in uint32.  1 <= max_len <= 32, alphabet_size <= 65536.
+ * in uint32.  1 <= max_len <= 32.
+ *
+ * Symbol widths.  The decoders the paper starts from took one-byte symbols;
+ * it adapts them to multi-byte quantization codes (Sec. IV) and notes that
+ * the technique carries over to double-precision data (Sec. V-A-3), whose
+ * codes can need a wider integer.  A stream's symbols are unsigned integers
+ * of symbol_bytes = 1, 2 or 4 bytes (0 is read as 2), and the alphabet must
+ * fit the width: alphabet_size <= 256, 65536 or HD_MAX_ALPHABET (2^24).  The
+ * bitstream itself does not depend on the width; the width fixes the output
+ * array's element type (and so the decoded bytes).  The batched, served,
+ * Algorithm-2 and reconstruction entry points take 2-byte symbols only.
  *
  * Conventions for every entry point:
  *   - ownership: the caller owns every buffer; the only library-owned object
@@ -54,6 +64,8 @@
 
 #include <stddef.h>
 #include <stdint.h>
+
+#define HD_MAX_ALPHABET (1u << 24)
 
 #ifdef __cplusplus
 extern "C" {
@@ -79,6 +91,7 @@ typedef enum {
 typedef struct {
     uint32_t subseq_bits;     /* S: bits per subsequence, multiple of 32, >= 32  */
     uint32_t chunk_subseqs;   /* C: subsequences per chunk, >= 1                 */
+    uint32_t symbol_bytes;    /* width of a symbol: 1, 2 or 4 (0 = 2)            */
 } hd_layout;
 
 typedef struct {
@@ -91,6 +104,8 @@ typedef struct {
     uint32_t chunk_subseqs;   /* C */
     uint32_t alphabet_size;   /* A */
     uint32_t max_len;         /* L */
+    uint32_t symbol_bytes;    /* width of a decoded symbol: 1, 2 or 4 (0 = 2)    */
+    uint32_t reserved;        /* set to 0                                        */
 } hd_stream_info;
 
 typedef struct hd_table hd_table;
@@ -129,21 +144,25 @@ typedef struct {
  * ranked by (count, symbol) and, at equal weight, a single symbol ranks
  * before a merged pair.  One used symbol gets length 1; none gives an empty
  * code.  Returns HD_ERR_INFEASIBLE when more than 2^L symbols are used,
- * HD_ERR_ARG for A outside [1, 65536] or L outside [1, 32].  Synchronous.
+ * HD_ERR_ARG for A outside [1, HD_MAX_ALPHABET] or L outside [1, 32].
+ * Synchronous.
  */
 hd_status hd_build_codebook(const uint64_t *hist, uint32_t A, uint32_t L,
                             uint8_t *lengths, uint32_t *codes);
 
 /*
- * Reference encoder (host): packs syms[n] with the codebook into the stream
- * format above and emits the gap array (Sec. III-C) and the chunk offsets.
- * Two-call use: with words == NULL only *info is filled (sizes); then call
- * again with buffers of at least info->n_words / n_subseq / n_chunks + 1
- * entries.  Returns HD_ERR_SYMBOL for a symbol >= A or without a
- * codeword, HD_ERR_ARG for a bad layout (S not a positive multiple of 32,
- * C == 0) or short buffers.  The codebook need not be canonical.  Synchronous.
+ * Reference encoder (host): packs syms[n] (unsigned integers of
+ * lay->symbol_bytes bytes each) with the codebook into the stream format
+ * above and emits the gap array (Sec. III-C) and the chunk offsets.
+ * Two-call use: with words == NULL only *info is filled (sizes, and the
+ * symbol width); then call again with buffers of at least info->n_words /
+ * n_subseq / n_chunks + 1 entries.  Returns HD_ERR_SYMBOL for a symbol >= A
+ * or without a codeword, HD_ERR_ARG for a bad layout (S not a positive
+ * multiple of 32, C == 0, a width other than 0, 1, 2, 4), an alphabet that
+ * does not fit the width, or short buffers.  The codebook need not be
+ * canonical.  Synchronous.
  */
-hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8_t *lengths,
+hd_status hd_encode_ref(const void *syms, uint64_t n, const uint8_t *lengths,
                         const uint32_t *codes, uint32_t A, uint32_t L, const hd_layout *lay,
                         uint32_t *words, uint64_t words_cap, uint8_t *gap, uint64_t gap_cap,
                         uint64_t *chunk_offsets, uint64_t chunk_cap, hd_stream_info *info);
@@ -152,9 +171,11 @@ hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8_t *lengths
  * The stream-format sizes of n_symbols symbols coded in n_bits bits under
  * *lay, alphabet A and length limit L: fills *info (n_words = n_subseq * S /
  * 32 + 2, n_subseq = ceil(n_bits / S), n_chunks = ceil(n_subseq / C); the
- * chunk-offset array has n_chunks + 1 entries).  HD_ERR_ARG for a bad layout
- * (S not a positive multiple of 32, C == 0), A outside [1, 65536] or L outside
- * [1, 32]; HD_ERR_CORRUPT when n_bits is outside [n_symbols, n_symbols * L].
+ * chunk-offset array has n_chunks + 1 entries; symbol_bytes = the layout's
+ * width).  HD_ERR_ARG for a bad layout (S not a positive multiple of 32,
+ * C == 0, a width other than 0, 1, 2, 4), an alphabet A that does not fit the
+ * width or L outside [1, 32]; HD_ERR_CORRUPT when n_bits is outside
+ * [n_symbols, n_symbols * L].
  * Synchronous, host only.
  */
 hd_status hd_stream_layout(uint64_t n_symbols, uint64_t n_bits, uint32_t A, uint32_t L, const hd_layout *lay,
@@ -170,9 +191,9 @@ hd_status hd_stream_layout(uint64_t n_symbols, uint64_t n_bits, uint32_t A, uint
  * longer codewords.  The paper keeps its codebook in global memory and relies
  * on the cache (Sec. IV-B); here each workgroup copies the first level and
  * the limits into LDS.  The upload is enqueued on hip_stream; the table may
- * be used by later work on that stream at once.  Returns HD_ERR_UNSUPPORTED
- * for a non-canonical codebook.  *out is owned by the caller until
- * hd_table_destroy.
+ * be used by later work on that stream at once.  Alphabets up to
+ * HD_MAX_ALPHABET.  Returns HD_ERR_UNSUPPORTED for a non-canonical codebook.
+ * *out is owned by the caller until hd_table_destroy.
  */
 hd_status hd_table_create(const uint8_t *lengths, const uint32_t *codes, uint32_t A, uint32_t L,
                           uint32_t lut_bits, void *hip_stream, hd_table **out);
@@ -197,7 +218,9 @@ hd_status hd_decode_workspace_size(const hd_dstream *s, hd_mode m, const hd_tune
                                    size_t *bytes);
 
 /*
- * Decodes one stream into out[0 .. n_symbols) (device memory).
+ * Decodes one stream into out[0 .. n_symbols) (device memory, 16-byte
+ * aligned), an array of unsigned integers of info.symbol_bytes bytes (the
+ * alphabet must fit that width; HD_ERR_ARG otherwise).
  * HD_MODE_GAP: each subsequence starts at k*S + gap[k] (Sec. III-C); output
  * indices are the stored chunk offsets, refined per subsequence by a
  * wavefront scan of decoded counts (Sec. III-B, step 3); symbols are staged
@@ -213,7 +236,7 @@ hd_status hd_decode_workspace_size(const hd_dstream *s, hd_mode m, const hd_tune
  * hd_decode_workspace_size), HD_ERR_DEVICE for launch failures.  Faults in
  * the data are reported by hd_decode_status.
  */
-hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
+hd_status hd_decode(const hd_dstream *s, void *out, hd_mode m, const hd_tune *tune,
                     void *workspace, size_t ws_bytes, void *hip_stream);
 
 /*
@@ -228,7 +251,7 @@ hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune
  */
 hd_status hd_decode_prepare(const hd_dstream *s, hd_mode m, const hd_tune *tune, void *workspace,
                             size_t ws_bytes, void *hip_stream);
-hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
+hd_status hd_decode_run(const hd_dstream *s, void *out, hd_mode m, const hd_tune *tune,
                         void *workspace, size_t ws_bytes, void *hip_stream);
 
 /*
@@ -320,7 +343,7 @@ hd_status hd_decode_cr_classes(const hd_dstream *s, uint16_t *out, void *workspa
  * hd_decode on this sample (their contents are overwritten).  Synchronous:
  * waits for hip_stream.
  */
-hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *out, void *workspace,
+hd_status hd_autotune(const hd_dstream *sample, hd_mode m, void *out, void *workspace,
                       size_t ws_bytes, void *hip_stream, hd_tune *best, float *best_ms);
 
 /*
@@ -346,6 +369,7 @@ hd_status hd_decode_status(const void *workspace, void *hip_stream);
  * for hip_stream first.
  */
 uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream);
+
 
 /* ------------------------------------------------------------ encoding -- */
 
@@ -376,6 +400,27 @@ uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream);
  *   word) instead of writing.
  */
 hd_status hd_histogram(const uint16_t *syms, uint64_t n, uint32_t A, uint64_t *hist, void *hip_stream);
+
+/*
+ * The codebook of hd_build_codebook, built on the device from a device
+ * histogram: lengths[A] (uint8) and codes[A] (uint32, right-aligned), device
+ * memory, byte for byte what hd_build_codebook returns for the same counts
+ * (optimal lengths <= L by package-merge, ties ranked by (count, symbol) with
+ * a symbol ahead of a pair of equal weight; canonical codes).  The paper
+ * takes the codebook from its encoder's GPU builder (Sec. II-B, Sec. VI); this
+ * keeps a device encode (hd_histogram, this call, hd_encode_plan/_write) free
+ * of host round trips.  One workgroup builds it in LDS: at most 4096 used
+ * symbols, A <= 65536 (HD_ERR_UNSUPPORTED above), counts below 2^40.  Data-
+ * dependent failures are reported through the workspace status word
+ * (hd_decode_status_bits(workspace)): bit 8 more used symbols than 2^L,
+ * bit 9 more than 4096 used symbols, bit 10 a count of 2^40 or more; the
+ * codebook is then all zero.  workspace: hd_codebook_workspace_size(L) bytes,
+ * 256-byte aligned, no initialization.  Asynchronous on hip_stream.
+ */
+size_t hd_codebook_workspace_size(uint32_t L);
+hd_status hd_build_codebook_device(const uint64_t *hist, uint32_t A, uint32_t L, uint8_t *lengths,
+                                   uint32_t *codes, void *workspace, size_t ws_bytes, void *hip_stream);
+
 size_t hd_encode_workspace_size(uint64_t n, uint32_t L, const hd_layout *lay);
 hd_status hd_encode_plan(const uint16_t *syms, uint64_t n, const uint8_t *lengths, uint32_t A, void *workspace,
                          size_t ws_bytes, void *hip_stream);

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhd.so")
-SOURCES = ["hd_host.cpp", "hd_device.hip", "hd_lorenzo.hip", "hd_encode.hip", "hd_serve.cpp"]
+SOURCES = ["hd_host.cpp", "hd_device.hip", "hd_lorenzo.hip", "hd_encode.hip", "hd_codebook.hip", "hd_serve.cpp"]
 ARCH = os.environ.get("HD_OFFLOAD_ARCH", "gfx950")
 
 

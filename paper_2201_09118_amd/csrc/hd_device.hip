@@ -82,8 +82,8 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 //
 // Device image (one allocation):
 //   lut   uint32[2^k1]   indexed by the next k1 stream bits.  Single format:
-//                        entry = symbol | length << 16 for codewords of at
-//                        most k1 bits; length kLenLong for a prefix of a
+//                        entry = symbol | length << 24 for codewords of at
+//                        most k1 bits (symbols below 2^24); length kLenLong for a prefix of a
 //                        longer codeword, kLenBad for a prefix of no
 //                        codeword (for both, the symbol field holds the
 //                        length the per-length search starts at: the
@@ -103,7 +103,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 //                        below theirs) holds a codeword of length l;
 //   base  int64[33]      base[l] = index of the first length-l symbol in
 //                        `syms` minus the first code of length l;
-//   syms  uint16[n_used] used symbols sorted by (length, symbol).
+//   syms  uint32[n_used] used symbols sorted by (length, symbol).
 
 struct hd_table {
     void *image = nullptr;
@@ -122,7 +122,7 @@ struct TableView {
     const uint32_t *lut;
     const uint64_t *lim;
     const int64_t *base;
-    const uint16_t *syms;
+    const uint32_t *syms;
     uint32_t k1, L;
 };
 
@@ -132,7 +132,7 @@ inline TableView view_of(const hd_table *t)
     return TableView{reinterpret_cast<const uint32_t *>(p + t->lut_off),
                      reinterpret_cast<const uint64_t *>(p + t->lim_off),
                      reinterpret_cast<const int64_t *>(p + t->base_off),
-                     reinterpret_cast<const uint16_t *>(p + t->syms_off), t->k1, t->L};
+                     reinterpret_cast<const uint32_t *>(p + t->syms_off), t->k1, t->L};
 }
 
 __host__ __device__ __forceinline__ uint32_t table_lds_bytes(uint32_t k1)
@@ -146,7 +146,7 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
                                      uint32_t L, uint32_t lut_bits, void *hip_stream,
                                      hd_table **out)
 {
-    if (!lengths || !codes || !out || A == 0 || A > 65536 || L == 0 || L > 32)
+    if (!lengths || !codes || !out || A == 0 || A > HD_MAX_ALPHABET || L == 0 || L > 32)
         return HD_ERR_ARG;
     if (lut_bits != 0 && (lut_bits < 6 || lut_bits > 14))
         return HD_ERR_ARG;
@@ -178,16 +178,16 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
             offs[l] = o;
             o += bl[l];
         }
-        std::vector<uint16_t> syms(std::max<uint32_t>(n_used, 1), 0);
+        std::vector<uint32_t> syms(std::max<uint32_t>(n_used, 1), 0);
         {
             uint64_t fill[34];
             std::memcpy(fill, offs, sizeof(fill));
             for (uint32_t s = 0; s < A; ++s)
                 if (lengths[s])
-                    syms[fill[lengths[s]]++] = static_cast<uint16_t>(s);
+                    syms[fill[lengths[s]]++] = s;
         }
         const uint32_t nlut = 1u << k1;
-        std::vector<uint32_t> lut(nlut, (kLenBad << 16) | (k1 + 1));
+        std::vector<uint32_t> lut(nlut, (kLenBad << 24) | (k1 + 1));
         // a prefix of longer codewords: the search over lengths starts at
         // the shortest codeword under it (every shorter length fails its
         // limit test for a canonical code)
@@ -195,8 +195,8 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
             const uint32_t l = lengths[s];
             if (l > k1) {
                 uint32_t &e = lut[codes[s] >> (l - k1)];
-                const uint32_t cur = (e >> 16) == kLenLong ? (e & 0x3fu) : 64u;
-                e = (kLenLong << 16) | std::min(cur, l);
+                const uint32_t cur = (e >> 24) == kLenLong ? (e & 0x3fu) : 64u;
+                e = (kLenLong << 24) | std::min(cur, l);
             }
         }
         for (uint32_t s = 0; s < A; ++s) {
@@ -205,19 +205,19 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
                 continue;
             const uint32_t lo = codes[s] << (k1 - l), hi = (codes[s] + 1) << (k1 - l);
             for (uint32_t w = lo; w < hi; ++w)
-                lut[w] = s | (l << 16);
+                lut[w] = s | (l << 24);
         }
         if (pair) {
             std::vector<uint32_t> two(nlut, 0);
             for (uint32_t w = 0; w < nlut; ++w) {
-                const uint32_t e = lut[w], l1 = e >> 16;
+                const uint32_t e = lut[w], l1 = e >> 24;
                 if (l1 == kLenLong || l1 == kLenBad) {
                     two[w] = e & 0x3fu;                  // len1 + len2 = 0: per-length limits
                     continue;
                 }
                 uint32_t v = (e & 0xfffu) | (l1 << 12);
                 if (l1 < k1) {
-                    const uint32_t e2 = lut[(w << l1) & (nlut - 1)], l2 = e2 >> 16;
+                    const uint32_t e2 = lut[(w << l1) & (nlut - 1)], l2 = e2 >> 24;
                     if (l2 != kLenLong && l2 != kLenBad && l2 <= k1 - l1)
                         v = (e & 0xfffu) | ((l1 + l2) << 12) | ((e2 & 0xfffu) << 16) | (l2 << 28);
                 }
@@ -244,7 +244,7 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
         t->lim_off = align_up(size_t(4) * nlut, 16);
         t->base_off = t->lim_off + 33 * 8;
         t->syms_off = align_up(t->base_off + 33 * 8, 16);
-        t->bytes = align_up(t->syms_off + 2 * syms.size(), 256);
+        t->bytes = align_up(t->syms_off + 4 * syms.size(), 256);
         if (hipGetDevice(&t->device) != hipSuccess) {
             delete t;
             return HD_ERR_DEVICE;
@@ -253,7 +253,7 @@ extern "C" hd_status hd_table_create(const uint8_t *lengths, const uint32_t *cod
         std::memcpy(img.data() + t->lut_off, lut.data(), 4 * nlut);
         std::memcpy(img.data() + t->lim_off, lim.data(), 33 * 8);
         std::memcpy(img.data() + t->base_off, base.data(), 33 * 8);
-        std::memcpy(img.data() + t->syms_off, syms.data(), 2 * syms.size());
+        std::memcpy(img.data() + t->syms_off, syms.data(), 4 * syms.size());
         if (hipMalloc(&t->image, t->bytes) != hipSuccess) {
             delete t;
             return HD_ERR_NOMEM;
@@ -368,7 +368,7 @@ __device__ __forceinline__ uint32_t window_at(const uint32_t *TTl, uint32_t q)
 // searched from length l0 (from the slow first-level entry; at least k1 + 1).
 __device__ __forceinline__ uint32_t decode_long(uint32_t v, uint32_t l0, uint32_t k1, uint32_t L,
                                              const uint64_t *lim, const int64_t *base,
-                                             const uint16_t *syms, uint32_t *len_out)
+                                             const uint32_t *syms, uint32_t *len_out)
 {
     for (uint32_t l = max(l0, k1 + 1); l <= L; ++l) {
         const uint64_t c = static_cast<uint64_t>(v) >> (32 - l);
@@ -431,9 +431,9 @@ __device__ __forceinline__ void lookup(const uint32_t *TTl, uint32_t q, const Sm
         l1 = ((e >> 12) & 0xfu) - l2;
         slow = l1 + l2 == 0;
     } else {
-        s1 = e & 0xffffu;
+        s1 = e & 0xffffffu;
         s2 = 0;
-        l1 = e >> 16;
+        l1 = e >> 24;
         l2 = 0;
         slow = l1 - 1u >= g.k1;
     }
@@ -460,7 +460,7 @@ __device__ __forceinline__ bool entry_group(uint32_t e, uint32_t k1, uint32_t &a
         n = 1 + (e >= (1u << 28));
         return a != 0;
     }
-    a = e >> 16;
+    a = e >> 24;
     n = 1;
     return a - 1u < k1;
 }
@@ -510,7 +510,7 @@ __device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q,
             l2 = e1 >> 28;
             fast1 = a1 != 0;
         } else {
-            a1 = e1 >> 16;
+            a1 = e1 >> 24;
             l2 = 0;
             fast1 = a1 - 1u < k1;
         }
@@ -530,7 +530,7 @@ __device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q,
             m2 = e2 >> 28;
             fast2 = b2 != 0;
         } else {
-            b2 = e2 >> 16;
+            b2 = e2 >> 24;
             m2 = 0;
             fast2 = b2 - 1u < k1;
         }
@@ -634,27 +634,27 @@ __device__ __forceinline__ uint32_t count_walk_log(const uint32_t *TTl, uint32_t
 // log stays in registers; a store that would fall at or past cnt (the unused
 // half of a one-codeword group, codewords of the last iteration past the
 // subsequence end) goes to the lane's dummy slot.
-template <int CAP>
-__device__ __forceinline__ void replay_log(const uint32_t (&lg)[2 * CAP], uint32_t nlog, uint16_t *dst,
-                                           uint32_t cnt, uint16_t *dummy)
+template <int CAP, typename T>
+__device__ __forceinline__ void replay_log(const uint32_t (&lg)[2 * CAP], uint32_t nlog, T *dst,
+                                           uint32_t cnt, T *dummy)
 {
     // A checked store picks between two base addresses (the slot's and one
     // below the dummy) and keeps its own offset, so the check costs a compare
     // and a select.
-    uint16_t *const dm1 = dummy - 1;
+    T *const dm1 = dummy - 1;
     const uint32_t cm1 = cnt - 1;                 // cnt >= 1 whenever nlog >= 1
     uint32_t j = 0;
 #pragma unroll
     for (int i = 0; i < CAP; ++i) {
         if (static_cast<uint32_t>(i) < nlog) {
             const uint32_t e1 = lg[2 * i], e2 = lg[2 * i + 1];
-            uint16_t *p = dst + j;
-            p[0] = static_cast<uint16_t>(e1 & 0xfffu);   // an iteration's first codeword is always the lane's
-            (j < cm1 ? p : dm1)[1] = static_cast<uint16_t>((e1 >> 16) & 0xfffu);
+            T *p = dst + j;
+            p[0] = static_cast<T>(e1 & 0xfffu);   // an iteration's first codeword is always the lane's
+            (j < cm1 ? p : dm1)[1] = static_cast<T>((e1 >> 16) & 0xfffu);
             j += 1u + (e1 >= (1u << 28));
             p = dst + j;
-            (j < cnt ? p : dm1 + 1)[0] = static_cast<uint16_t>(e2 & 0xfffu);
-            (j < cm1 ? p : dm1)[1] = static_cast<uint16_t>((e2 >> 16) & 0xfffu);
+            (j < cnt ? p : dm1 + 1)[0] = static_cast<T>(e2 & 0xfffu);
+            (j < cm1 ? p : dm1)[1] = static_cast<T>((e2 >> 16) & 0xfffu);
             j += (e2 != 0 ? 1u : 0u) + (e2 >= (1u << 28));
         }
     }
@@ -757,7 +757,7 @@ struct StreamDev {
     const uint32_t *words;
     const uint8_t *gap;
     const uint64_t *chunk_off;   // [M + 1] output index of each chunk
-    uint16_t *out;
+    void *out;                   // n symbols of the kernel's output type
     uint64_t n, B, K, M, n_words;
     uint32_t S, stage;           // stage: staging symbols per wave (multiple of 64)
     uint32_t Cl;                 // log2 of the chunk size C (C divides 64)
@@ -816,9 +816,9 @@ __device__ __forceinline__ uint32_t *tt_of(unsigned char *area, int lane)
     return reinterpret_cast<uint32_t *>(area) - 64 + lane;
 }
 
-__host__ __device__ __forceinline__ uint32_t wave_area_bytes(uint32_t S, uint32_t stage)
+__host__ __device__ __forceinline__ uint32_t wave_area_bytes(uint32_t S, uint32_t stage, uint32_t sym_bytes = 2)
 {
-    return wave_units_bytes(S) + 2 * stage + 128;
+    return wave_units_bytes(S) + sym_bytes * (stage + 64);
 }
 
 // A lane's inputs for one tile: its subsequence's units and the next unit,
@@ -886,31 +886,39 @@ struct TileInT {
     }
 };
 
+// Symbols of type T in one 16-byte group.
+template <typename T>
+constexpr uint32_t kGroup = 16 / sizeof(T);
+
 // Writes staged output [g0, g1) (global indices; the stage starts at the
 // 16-byte group holding g0): whole 16-byte groups with one 16-byte store per
-// lane, then the partial groups at both ends (at most 7 symbols each) with one
-// 2-byte store per lane on lanes 0-15, so no lane walks a group symbol by
-// symbol.  Offsets are relative to that first group (32-bit).
-__device__ __forceinline__ void flush_stage(const StreamDev &sd, const uint16_t *stage, int lane, uint64_t g0,
+// lane, then the partial groups at both ends (at most G - 1 symbols each, G
+// = symbols per group) with one symbol store per lane on lanes 0 .. 2G-1, so
+// no lane walks a group symbol by symbol.  Offsets are relative to that first
+// group (32-bit).
+template <typename T>
+__device__ __forceinline__ void flush_stage(const StreamDev &sd, const T *stage, int lane, uint64_t g0,
                                             uint64_t g1, uint32_t &err)
 {
+    constexpr uint32_t G = kGroup<T>;
     if (g1 > sd.n) {
         err |= kErrOutRange;
         g1 = sd.n;
     }
     if (g0 < g1) {
-        const uint64_t gb0 = g0 & ~uint64_t(7);
-        uint16_t *const out = sd.out + gb0;
-        const uint32_t h0 = static_cast<uint32_t>(g0 - gb0);      // first symbol, 0..7
+        const uint64_t gb0 = g0 & ~uint64_t(G - 1);
+        T *const out = static_cast<T *>(sd.out) + gb0;
+        const uint32_t h0 = static_cast<uint32_t>(g0 - gb0);      // first symbol, 0..G-1
         const uint32_t e1 = static_cast<uint32_t>(g1 - gb0);      // end
-        const uint32_t f0 = (h0 + 7) & ~7u;                       // first whole group
-        const uint32_t f1 = e1 & ~7u;                             // end of whole groups
-        for (uint32_t o = f0 + 8 * lane; o < f1; o += 8 * 64)
+        const uint32_t f0 = (h0 + G - 1) & ~(G - 1);              // first whole group
+        const uint32_t f1 = e1 & ~(G - 1);                        // end of whole groups
+        for (uint32_t o = f0 + G * lane; o < f1; o += G * 64)
             *reinterpret_cast<uint4 *>(out + o) = *reinterpret_cast<const uint4 *>(stage + o);
-        // head [h0, min(f0, e1)) on lanes 0-7, tail [max(f1, f0), e1) on lanes 8-15
-        const uint32_t o = lane < 8 ? h0 + lane : max(f1, f0) + (lane - 8);
-        const uint32_t lim = lane < 8 ? min(f0, e1) : e1;
-        if (lane < 16 && o < lim)
+        // head [h0, min(f0, e1)) on lanes 0..G-1, tail [max(f1, f0), e1) on lanes G..2G-1
+        const uint32_t ul = static_cast<uint32_t>(lane);
+        const uint32_t o = ul < G ? h0 + ul : max(f1, f0) + (ul - G);
+        const uint32_t lim = ul < G ? min(f0, e1) : e1;
+        if (ul < 2 * G && o < lim)
             out[o] = stage[o];
     }
 }
@@ -922,40 +930,41 @@ __device__ __forceinline__ void flush_stage(const StreamDev &sd, const uint16_t 
 // itself.  A group's two symbols go out as two 16-bit stores: the compiler
 // would merge them into one 32-bit store at a 2-byte-aligned LDS address,
 // which measured far slower (the scheduling barrier keeps them apart).
-template <bool PAIR>
+template <bool PAIR, typename T>
 __device__ __forceinline__ void walk_symbols(const uint32_t *TTl, uint32_t &q, uint32_t &j, uint32_t jmax,
-                                             uint16_t *dst, uint16_t *dummy, const SmemTable &st,
+                                             T *dst, T *dummy, const SmemTable &st,
                                              const TableView &g, uint32_t sh, uint32_t &err)
 {
     const uint32_t k1 = g.k1;
     constexpr uint32_t kFastMin = PAIR ? 4u : 2u;
     if (j + kFastMin <= jmax) {
-        uint16_t *pd = dst + j;
-        const uint16_t *const pend = dst + (jmax - kFastMin);
+        T *pd = dst + j;
+        const T *const pend = dst + (jmax - kFastMin);
         do {
             const uint32_t v = window_at(TTl, q);
             const uint32_t e1 = st.lut[v >> sh];
             uint32_t a1, n1, a2, n2;
             const bool fast1 = entry_group<PAIR>(e1, k1, a1, n1);
-            uint32_t w1 = PAIR ? (e1 & 0x0fff0fffu) : (e1 & 0xffffu);
+            uint32_t w1 = PAIR ? (e1 & 0x0fff0fffu) : (e1 & 0xffffffu);
             if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
                 if (!fast1)
                     w1 = slow_group(v, e1, st, g, a1, n1, err);
             }
-            pd[0] = static_cast<uint16_t>(w1);
+            // (a pair entry holds its second symbol in the upper half)
+            pd[0] = static_cast<T>(PAIR ? (w1 & 0xffffu) : w1);
             __builtin_amdgcn_sched_barrier(0);
             if (PAIR)
-                pd[1] = static_cast<uint16_t>(w1 >> 16);
+                pd[1] = static_cast<T>(w1 >> 16);
             pd += n1;
             const uint32_t e2 = st.lut[(v << (a1 & 31u)) >> sh];
             const bool take2 = entry_group<PAIR>(e2, k1, a2, n2) && fast1;
             if (PAIR) {
                 const uint32_t w2 = e2 & 0x0fff0fffu;
-                pd[0] = static_cast<uint16_t>(w2);
+                pd[0] = static_cast<T>(w2 & 0xffffu);
                 __builtin_amdgcn_sched_barrier(0);
-                pd[1] = static_cast<uint16_t>(w2 >> 16);
+                pd[1] = static_cast<T>(w2 >> 16);
             } else {
-                *pd = static_cast<uint16_t>(e2 & 0xffffu);
+                *pd = static_cast<T>(e2 & 0xffffffu);
             }
             pd += take2 ? n2 : 0u;
             q += a1 + (take2 ? a2 : 0u);
@@ -965,13 +974,13 @@ __device__ __forceinline__ void walk_symbols(const uint32_t *TTl, uint32_t &q, u
     while (j < jmax) {
         uint32_t s1, s2, l1, l2;
         lookup<PAIR>(TTl, q, st, g, sh, s1, s2, l1, l2, err);
-        dst[j] = static_cast<uint16_t>(s1);
+        dst[j] = static_cast<T>(s1);
         ++j;
         if (PAIR) {
             // second codeword: stored when it is this lane's and in this
             // pass, else written to the lane's dummy slot
             const bool two = l2 != 0 && j < jmax;
-            *(two ? dst + j : dummy) = static_cast<uint16_t>(s2);
+            *(two ? dst + j : dummy) = static_cast<T>(s2);
             j += two;
             l1 += two ? l2 : 0u;
         }
@@ -982,15 +991,16 @@ __device__ __forceinline__ void walk_symbols(const uint32_t *TTl, uint32_t &q, u
 // Steps 2-4 for one wavefront tile whose units are already in TT.  With
 // CAP > 0 (pair format) the count step logs its table entries and a tile whose
 // output fits one staging pass is decoded by replaying them.
-template <bool PAIR, int CAP>
+template <bool PAIR, int CAP, typename T>
 __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int lane, uint32_t gk_in,
                                             uint32_t gn, uint64_t c_lo, uint64_t c_hi, const uint32_t *TTl,
-                                            uint16_t *stage, uint16_t *dummy, const SmemTable &st,
+                                            T *stage, T *dummy, const SmemTable &st,
                                             const TableView &g, uint32_t sh, uint32_t &err)
 {
     static_assert(CAP == 0 || PAIR, "the entry log holds pair-format entries");
+    constexpr uint32_t G = kGroup<T>;
     const uint32_t S = sd.S;
-    const uint32_t PB = sd.stage - 8;
+    const uint32_t PB = sd.stage - G;
     const uint64_t k0 = t << 6;                       // wavefront-uniform
     const uint64_t left = sd.K - k0;                  // subsequences from k0 on (>= 1)
     const uint32_t l = static_cast<uint32_t>(lane);
@@ -1041,10 +1051,10 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
     }
 
     // 4. decode into LDS staging, flush with 16-byte stores
-    const uint32_t a0 = static_cast<uint32_t>(gbase & 7);
+    const uint32_t a0 = static_cast<uint32_t>(gbase & (G - 1));
     if constexpr (CAP > 0) {
         if (total <= PB) {
-            uint16_t *dst = stage + (a0 + excl);
+            T *dst = stage + (a0 + excl);
             replay_log<CAP>(lg, nlog, dst, cnt, dummy);
             const bool more = q_cap < qe;               // went on past the log
             if (__builtin_amdgcn_ballot_w64(more) != 0) {
@@ -1065,7 +1075,7 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
         const uint32_t lim_rel = pb + PB;
         const uint32_t jmax = lim_rel > excl ? min(cnt, lim_rel - excl) : 0u;
         // dst index of symbol j: a0 + excl + j - pb (>= a0 whenever j < jmax)
-        uint16_t *dst = stage + (static_cast<int32_t>(a0 + excl) - static_cast<int32_t>(pb));
+        T *dst = stage + (static_cast<int32_t>(a0 + excl) - static_cast<int32_t>(pb));
         walk_symbols<PAIR>(TTl, q, j, jmax, dst, dummy, st, g, sh, err);
         wave_lds_sync();
         flush_stage(sd, stage, lane, gbase + pb, gbase + min(lim_rel, total), err);
@@ -1078,7 +1088,7 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
 // rest of a lane is walked.
 constexpr int kLogIters = 12;
 
-template <bool PAIR, uint32_t MAXU, bool LISTED = false>
+template <bool PAIR, uint32_t MAXU, bool LISTED = false, typename T = uint16_t>
 __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -1091,10 +1101,10 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
     const int lane = threadIdx.x & 63;
     const int wv = wave_index();
     const uint32_t wps = sd.S >> 5;
-    unsigned char *area = smem + table_lds_bytes(g.k1) + wv * wave_area_bytes(sd.S, sd.stage);
+    unsigned char *area = smem + table_lds_bytes(g.k1) + wv * wave_area_bytes(sd.S, sd.stage, sizeof(T));
     uint32_t *TTl = tt_of(area, lane);
-    uint16_t *stage = reinterpret_cast<uint16_t *>(area + wave_units_bytes(sd.S));
-    uint16_t *dummy = stage + sd.stage + lane;
+    T *stage = reinterpret_cast<T *>(area + wave_units_bytes(sd.S));
+    T *dummy = stage + sd.stage + lane;
     const uint32_t sh = 32 - g.k1;
 
     uint32_t err = 0;
@@ -1823,17 +1833,25 @@ uint32_t reg_waves_per_cu(const void *func)
     return waves;
 }
 
-template <bool PAIR>
+template <bool PAIR, typename T>
 const void *gap_kernel_of(uint32_t S)
 {
-    return S <= 32 * kSmallUnits ? reinterpret_cast<const void *>(&k_decode_gap<PAIR, kSmallUnits>)
-                                 : reinterpret_cast<const void *>(&k_decode_gap<PAIR, kMaxUnitsPerLane>);
+    return S <= 32 * kSmallUnits ? reinterpret_cast<const void *>(&k_decode_gap<PAIR, kSmallUnits, false, T>)
+                                 : reinterpret_cast<const void *>(&k_decode_gap<PAIR, kMaxUnitsPerLane, false, T>);
 }
 
-const void *gap_kernel(bool pair, uint32_t S)
+// The decode kernel for a table format, subsequence size and symbol width.
+const void *gap_kernel(bool pair, uint32_t S, uint32_t w = 2)
 {
-    return pair ? gap_kernel_of<true>(S) : gap_kernel_of<false>(S);
+    if (w == 1)
+        return pair ? gap_kernel_of<true, uint8_t>(S) : gap_kernel_of<false, uint8_t>(S);
+    if (w == 4)
+        return pair ? gap_kernel_of<true, uint32_t>(S) : gap_kernel_of<false, uint32_t>(S);
+    return pair ? gap_kernel_of<true, uint16_t>(S) : gap_kernel_of<false, uint16_t>(S);
 }
+
+// Symbol width of a stream (0 reads as 2).
+inline uint32_t sym_bytes(const hd_stream_info &i) { return i.symbol_bytes ? i.symbol_bytes : 2u; }
 
 hd_status check_stream(const hd_dstream *s, hd_mode m)
 {
@@ -1848,6 +1866,11 @@ hd_status check_stream(const hd_dstream *s, hd_mode m)
     if (i.chunk_subseqs == 0)
         return HD_ERR_ARG;
     if (i.alphabet_size != t->A || i.max_len != t->L)
+        return HD_ERR_ARG;
+    // the alphabet must fit the symbol width
+    const uint32_t w = sym_bytes(i);
+    if (!((w == 1 && i.alphabet_size <= 256u) || (w == 2 && i.alphabet_size <= 65536u) ||
+          (w == 4 && i.alphabet_size <= HD_MAX_ALPHABET)))
         return HD_ERR_ARG;
     const uint64_t K = ceil_div(i.n_bits, i.subseq_bits);
     if (i.n_subseq != K || i.n_chunks != ceil_div(K, i.chunk_subseqs))
@@ -1953,7 +1976,7 @@ uint32_t occupancy_stage(const hd_stream_info &si, uint32_t table, uint32_t reg_
     uint32_t best = hi, best_waves = 0;
     for (uint32_t st = hi; st >= lo; st -= 64) {
         uint32_t waves = 0;
-        occupancy_wpg(table, wave_area_bytes(si.subseq_bits, st), dev, &waves, reg_cap, func);
+        occupancy_wpg(table, wave_area_bytes(si.subseq_bits, st, sym_bytes(si)), dev, &waves, reg_cap, func);
         if (waves > best_waves) {
             best = st;
             best_waves = waves;
@@ -1970,14 +1993,14 @@ hd_status make_plan(const hd_dstream *s, const hd_tune *tune, Plan *p)
     if (!dev)
         return HD_ERR_DEVICE;
     const uint32_t S = s->info.subseq_bits;
-    const void *func = gap_kernel(s->table->pair, S);
+    const void *func = gap_kernel(s->table->pair, S, sym_bytes(s->info));
     const uint32_t reg_cap = reg_waves_per_cu(func);
     const uint32_t table = table_lds_bytes(s->table->k1);
     p->stage = tune && tune->stage_symbols ? tune->stage_symbols
                                            : occupancy_stage(s->info, table, reg_cap, dev, func);
     if (p->stage < 256 || p->stage > 16384 || p->stage % 64)
         return HD_ERR_ARG;
-    const uint32_t area = wave_area_bytes(S, p->stage);
+    const uint32_t area = wave_area_bytes(S, p->stage, sym_bytes(s->info));
     p->wpg = tune && tune->waves_per_group ? tune->waves_per_group
                                            : occupancy_wpg(table, area, dev, nullptr, reg_cap, func);
     if (p->wpg == 0)
@@ -2102,13 +2125,24 @@ hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, h
                           : launch_sync<kWpg, false>(a, grid, lds, stream);
 }
 
-template <bool PAIR, uint32_t MAXU>
+template <bool PAIR, uint32_t MAXU, typename T = uint16_t>
 hd_status launch_gap(const GapArgs &a, const Plan &p, hipStream_t stream)
 {
-    if (!allow_full_lds(reinterpret_cast<const void *>(&k_decode_gap<PAIR, MAXU>)))
+    if (!allow_full_lds(reinterpret_cast<const void *>(&k_decode_gap<PAIR, MAXU, false, T>)))
         return HD_ERR_DEVICE;
-    hipLaunchKernelGGL((k_decode_gap<PAIR, MAXU>), dim3(p.grid), dim3(p.wpg * 64), p.lds_bytes, stream, a);
+    hipLaunchKernelGGL((k_decode_gap<PAIR, MAXU, false, T>), dim3(p.grid), dim3(p.wpg * 64), p.lds_bytes, stream,
+                       a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
+}
+
+template <typename T>
+hd_status launch_gap_as(const GapArgs &a, const Plan &p, bool pair, bool small, hipStream_t stream)
+{
+    if (pair)
+        return small ? launch_gap<true, kSmallUnits, T>(a, p, stream)
+                     : launch_gap<true, kMaxUnitsPerLane, T>(a, p, stream);
+    return small ? launch_gap<false, kSmallUnits, T>(a, p, stream)
+                 : launch_gap<false, kMaxUnitsPerLane, T>(a, p, stream);
 }
 
 // Enqueues the scan of per-tile totals (self-sync mode): off[0..M].
@@ -2207,7 +2241,7 @@ namespace {
 
 // The decode-and-write launch of a checked call.  direct: a caller-zeroed
 // status word (gap mode only; the workspace is then not used).
-hd_status run_decode_kernel(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune, void *workspace,
+hd_status run_decode_kernel(const hd_dstream *s, void *out, hd_mode m, const hd_tune *tune, void *workspace,
                             uint32_t *direct, hipStream_t stream)
 {
     hd_status st = HD_OK;
@@ -2243,14 +2277,17 @@ hd_status run_decode_kernel(const hd_dstream *s, uint16_t *out, hd_mode m, const
     a.n_list = 0;
     a.tab = view_of(s->table);
     const bool small = i.subseq_bits <= 32 * kSmallUnits;
-    if (s->table->pair)
-        return small ? launch_gap<true, kSmallUnits>(a, p, stream) : launch_gap<true, kMaxUnitsPerLane>(a, p, stream);
-    return small ? launch_gap<false, kSmallUnits>(a, p, stream) : launch_gap<false, kMaxUnitsPerLane>(a, p, stream);
+    const uint32_t wid = sym_bytes(i);
+    if (wid == 1)
+        return launch_gap_as<uint8_t>(a, p, s->table->pair, small, stream);
+    if (wid == 4)
+        return launch_gap_as<uint32_t>(a, p, s->table->pair, small, stream);
+    return launch_gap_as<uint16_t>(a, p, s->table->pair, small, stream);
 }
 
 }  // namespace
 
-extern "C" hd_status hd_decode_run(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
+extern "C" hd_status hd_decode_run(const hd_dstream *s, void *out, hd_mode m, const hd_tune *tune,
                                    void *workspace, size_t ws_bytes, void *hip_stream)
 {
     hd_status st = check_call(s, m, tune, workspace, ws_bytes);
@@ -2266,13 +2303,15 @@ hd_status hd::decode_gap_direct(const hd_dstream *s, uint16_t *out, uint32_t *st
     hd_status st = check_stream(s, HD_MODE_GAP);
     if (st != HD_OK)
         return st;
+    if (sym_bytes(s->info) != 2)
+        return HD_ERR_UNSUPPORTED;
     if (!status_word || (s->info.n_symbols && !out) || reinterpret_cast<uintptr_t>(out) % 16 != 0 ||
         reinterpret_cast<uintptr_t>(s->words) % 16 != 0)
         return HD_ERR_ARG;
     return run_decode_kernel(s, out, HD_MODE_GAP, nullptr, nullptr, status_word, static_cast<hipStream_t>(hip_stream));
 }
 
-extern "C" hd_status hd_decode(const hd_dstream *s, uint16_t *out, hd_mode m, const hd_tune *tune,
+extern "C" hd_status hd_decode(const hd_dstream *s, void *out, hd_mode m, const hd_tune *tune,
                                void *workspace, size_t ws_bytes, void *hip_stream)
 {
     hd_status st = check_call(s, m, tune, workspace, ws_bytes);
@@ -2381,6 +2420,8 @@ extern "C" hd_status hd_decode_cr_classes_workspace_size(const hd_dstream *s, si
     hd_status st = check_stream(s, HD_MODE_GAP);
     if (st != HD_OK)
         return st;
+    if (sym_bytes(s->info) != 2)
+        return HD_ERR_UNSUPPORTED;
     *bytes = cr_ws_bytes(ceil_div(s->info.n_subseq, 64));
     return HD_OK;
 }
@@ -2644,6 +2685,8 @@ extern "C" hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, u
         return HD_ERR_UNSUPPORTED;
     for (uint32_t i = 0; i < n_streams; ++i) {
         hd_status st = check_stream(&streams[i], m);
+        if (st == HD_OK && sym_bytes(streams[i].info) != 2)
+            st = HD_ERR_UNSUPPORTED;
         if (st != HD_OK)
             return st;
     }
@@ -2834,7 +2877,7 @@ hd_status hd::decode_batch_direct(const hd_dstream *streams, uint32_t n_streams,
                              status_word);
 }
 
-extern "C" hd_status hd_autotune(const hd_dstream *sample, hd_mode m, uint16_t *out, void *workspace,
+extern "C" hd_status hd_autotune(const hd_dstream *sample, hd_mode m, void *out, void *workspace,
                                  size_t ws_bytes, void *hip_stream, hd_tune *best, float *best_ms)
 {
     if (!best)
@@ -2940,3 +2983,4 @@ extern "C" hd_status hd_decode_status(const void *workspace, void *hip_stream)
         return HD_ERR_DEVICE;
     return v ? HD_ERR_CORRUPT : HD_OK;
 }
+

@@ -137,6 +137,19 @@ hd_status canonical_from_lengths(const uint8_t *len, uint32_t A, uint32_t L, uin
     return HD_OK;
 }
 
+// Symbol width of a layout (0 reads as 2) and whether alphabet A fits it.
+uint32_t layout_width(const hd_layout *lay) { return lay->symbol_bytes ? lay->symbol_bytes : 2u; }
+
+bool width_fits(uint32_t w, uint32_t A)
+{
+    return A != 0 && ((w == 1 && A <= 256u) || (w == 2 && A <= 65536u) || (w == 4 && A <= HD_MAX_ALPHABET));
+}
+
+template <typename T>
+hd_status encode_as(const T *syms, uint64_t n, const uint8_t *lengths, const uint32_t *codes, uint32_t A,
+                    uint32_t L, const hd_layout *lay, uint32_t *words, uint64_t words_cap, uint8_t *gap,
+                    uint64_t gap_cap, uint64_t *chunk_offsets, uint64_t chunk_cap, hd_stream_info *info);
+
 }  // namespace
 
 extern "C" hd_status hd_canonical_codes_internal(const uint8_t *len, uint32_t A, uint32_t L,
@@ -148,7 +161,7 @@ extern "C" hd_status hd_canonical_codes_internal(const uint8_t *len, uint32_t A,
 extern "C" hd_status hd_build_codebook(const uint64_t *hist, uint32_t A, uint32_t L,
                                        uint8_t *lengths, uint32_t *codes)
 {
-    if (!hist || !lengths || !codes || A == 0 || A > 65536 || L == 0 || L > 32)
+    if (!hist || !lengths || !codes || A == 0 || A > HD_MAX_ALPHABET || L == 0 || L > 32)
         return HD_ERR_ARG;
     try {
         hd_status st = lengths_package_merge(hist, A, L, lengths);
@@ -162,7 +175,7 @@ extern "C" hd_status hd_build_codebook(const uint64_t *hist, uint32_t A, uint32_
     }
 }
 
-extern "C" hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8_t *lengths,
+extern "C" hd_status hd_encode_ref(const void *syms, uint64_t n, const uint8_t *lengths,
                                    const uint32_t *codes, uint32_t A, uint32_t L,
                                    const hd_layout *lay, uint32_t *words, uint64_t words_cap,
                                    uint8_t *gap, uint64_t gap_cap, uint64_t *chunk_offsets,
@@ -170,8 +183,26 @@ extern "C" hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8
 {
     if (!lengths || !codes || !lay || !info || (n && !syms))
         return HD_ERR_ARG;
-    if (A == 0 || A > 65536 || L == 0 || L > 32)
+    const uint32_t w = layout_width(lay);
+    if (!width_fits(w, A) || L == 0 || L > 32)
         return HD_ERR_ARG;
+    if (w == 1)
+        return encode_as(static_cast<const uint8_t *>(syms), n, lengths, codes, A, L, lay, words, words_cap, gap,
+                         gap_cap, chunk_offsets, chunk_cap, info);
+    if (w == 2)
+        return encode_as(static_cast<const uint16_t *>(syms), n, lengths, codes, A, L, lay, words, words_cap, gap,
+                         gap_cap, chunk_offsets, chunk_cap, info);
+    return encode_as(static_cast<const uint32_t *>(syms), n, lengths, codes, A, L, lay, words, words_cap, gap,
+                     gap_cap, chunk_offsets, chunk_cap, info);
+}
+
+namespace {
+
+template <typename T>
+hd_status encode_as(const T *syms, uint64_t n, const uint8_t *lengths, const uint32_t *codes, uint32_t A,
+                    uint32_t L, const hd_layout *lay, uint32_t *words, uint64_t words_cap, uint8_t *gap,
+                    uint64_t gap_cap, uint64_t *chunk_offsets, uint64_t chunk_cap, hd_stream_info *info)
+{
     const uint32_t S = lay->subseq_bits, C = lay->chunk_subseqs;
     if (S < 32 || S % 32 != 0 || C == 0)
         return HD_ERR_ARG;
@@ -181,7 +212,7 @@ extern "C" hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8
 
     uint64_t B = 0;
     for (uint64_t i = 0; i < n; ++i) {
-        const uint16_t s = syms[i];
+        const uint32_t s = syms[i];
         if (s >= A || lengths[s] == 0)
             return HD_ERR_SYMBOL;
         B += lengths[s];
@@ -198,6 +229,8 @@ extern "C" hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8
     info->chunk_subseqs = C;
     info->alphabet_size = A;
     info->max_len = L;
+    info->symbol_bytes = layout_width(lay);
+    info->reserved = 0;
     if (!words)
         return HD_OK;
     if (words_cap < NW || gap_cap < K || chunk_cap < M + 1 || !chunk_offsets || (K && !gap))
@@ -212,7 +245,7 @@ extern "C" hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8
     uint64_t wi = 0;        // next unit to write
     uint64_t pos = 0;       // bit position of the current codeword
     for (uint64_t i = 0; i < n; ++i) {
-        const uint16_t s = syms[i];
+        const uint32_t s = syms[i];
         const uint32_t l = lengths[s];
         // Subsequence boundaries this codeword starts on or straddles: the
         // first codeword start at or after each is pos (on) or pos+l (inside).
@@ -245,10 +278,12 @@ extern "C" hd_status hd_encode_ref(const uint16_t *syms, uint64_t n, const uint8
     return HD_OK;
 }
 
+}  // namespace
+
 extern "C" hd_status hd_stream_layout(uint64_t n_symbols, uint64_t n_bits, uint32_t A, uint32_t L,
                                       const hd_layout *lay, hd_stream_info *info)
 {
-    if (!lay || !info || A == 0 || A > 65536 || L == 0 || L > 32)
+    if (!lay || !info || !width_fits(layout_width(lay), A) || L == 0 || L > 32)
         return HD_ERR_ARG;
     const uint32_t S = lay->subseq_bits, C = lay->chunk_subseqs;
     if (S < 32 || S % 32 != 0 || C == 0)
@@ -265,6 +300,8 @@ extern "C" hd_status hd_stream_layout(uint64_t n_symbols, uint64_t n_bits, uint3
     info->chunk_subseqs = C;
     info->alphabet_size = A;
     info->max_len = L;
+    info->symbol_bytes = layout_width(lay);
+    info->reserved = 0;
     return HD_OK;
 }
 

@@ -23,6 +23,9 @@ enum : uint32_t {
     kErrOutRange = 1u << 5,     // an output index fell outside [0, n)
     kErrNoSync = 1u << 6,       // the synchronized path does not end on the stream end
     kErrNoOutlier = 1u << 7,    // reconstruction: a code-0 position missing from the outlier list
+    kErrCbInfeasible = 1u << 8, // device codebook: more used symbols than 2^L codewords
+    kErrCbTooMany = 1u << 9,    // device codebook: more used symbols than one workgroup ranks
+    kErrCbCount = 1u << 10,     // device codebook: a count of 2^40 or more
 };
 
 // Library-internal decode calls for the serving loop (C++ linkage, not part

@@ -44,6 +44,8 @@ SIGNATURES = {
     "hd_decode_status_bits": (_u32, [_vp, _vp]),
     "hd_lorenzo_workspace_size": (_sz, [_u32, _u32, _u32]),
     "hd_histogram": (C.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "hd_codebook_workspace_size": (_sz, [_u32]),
+    "hd_build_codebook_device": (C.c_int, [_vp, _u32, _u32, _vp, _vp, _vp, _sz, _vp]),
     "hd_encode_workspace_size": (_sz, [_u64, _u32, _vp]),
     "hd_encode_plan": (C.c_int, [_vp, _u64, _vp, _u32, _vp, _sz, _vp]),
     "hd_encode_bits": (C.c_int, [_vp, C.POINTER(_u64), _vp]),
@@ -71,13 +73,14 @@ class HDError(RuntimeError):
 
 
 class Layout(C.Structure):
-    _fields_ = [("subseq_bits", C.c_uint32), ("chunk_subseqs", C.c_uint32)]
+    _fields_ = [("subseq_bits", C.c_uint32), ("chunk_subseqs", C.c_uint32), ("symbol_bytes", C.c_uint32)]
 
 
 class StreamInfo(C.Structure):
     _fields_ = [("n_symbols", C.c_uint64), ("n_bits", C.c_uint64), ("n_words", C.c_uint64),
                 ("n_subseq", C.c_uint64), ("n_chunks", C.c_uint64), ("subseq_bits", C.c_uint32),
-                ("chunk_subseqs", C.c_uint32), ("alphabet_size", C.c_uint32), ("max_len", C.c_uint32)]
+                ("chunk_subseqs", C.c_uint32), ("alphabet_size", C.c_uint32), ("max_len", C.c_uint32),
+                ("symbol_bytes", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Tune(C.Structure):
@@ -134,6 +137,20 @@ def _dev_ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _out_ptr(ds, out):
+    """Device pointer of a decode output tensor, checked against the stream's
+    symbol width and length (a short or narrower tensor would be overrun)."""
+    w = int(ds.info.symbol_bytes) or 2
+    n = int(ds.info.n_symbols)
+    if out is None:
+        if n:
+            raise ValueError("decode output is None")
+        return None
+    if out.element_size() != w or out.numel() < n or not out.is_contiguous():
+        raise ValueError(f"decode output must be a contiguous tensor of >= {n} elements of {w} bytes")
+    return _dev_ptr(out)
+
+
 def _stream_handle(stream):
     if stream is None:
         import torch
@@ -169,12 +186,19 @@ class HostStream:
         return int(self.info.n_bits)
 
 
+_WIDTH_OF = {np.dtype(np.uint8): 1, np.dtype(np.uint16): 2, np.dtype(np.uint32): 4}
+
+
 def encode_ref(syms: np.ndarray, lengths: np.ndarray, codes: np.ndarray, L: int,
                S: int = 128, Cc: int = 32) -> HostStream:
-    syms = np.ascontiguousarray(syms, dtype=np.uint16)
+    """hd_encode_ref; uint8 and uint32 symbol arrays keep their width, others are taken as uint16."""
+    syms = np.asarray(syms)
+    if syms.dtype not in _WIDTH_OF:
+        syms = syms.astype(np.uint16)
+    syms = np.ascontiguousarray(syms)
     lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
     codes = np.ascontiguousarray(codes, dtype=np.uint32)
-    lay = Layout(S, Cc)
+    lay = Layout(S, Cc, _WIDTH_OF[syms.dtype])
     info = StreamInfo()
     L_ = lib()
     _check(L_.hd_encode_ref(_np_ptr(syms), syms.size, _np_ptr(lengths), _np_ptr(codes), lengths.size, L,
@@ -282,7 +306,7 @@ def decode(ds: DeviceStream, out, mode: int = MODE_GAP, tune=None, workspace=Non
     d = ds.as_c()
     if workspace is None:
         workspace = alloc_workspace(decode_workspace_size(ds, mode, tune), out.device)
-    _check(lib().hd_decode(C.byref(d), _dev_ptr(out), mode, _tune_ptr(tune), _dev_ptr(workspace),
+    _check(lib().hd_decode(C.byref(d), _out_ptr(ds, out), mode, _tune_ptr(tune), _dev_ptr(workspace),
                            workspace.numel(), _stream_handle(stream)), "hd_decode")
     return workspace
 
@@ -295,7 +319,7 @@ def decode_prepare(ds: DeviceStream, workspace, mode: int = MODE_GAP, tune=None,
 
 def decode_run(ds: DeviceStream, out, workspace, mode: int = MODE_GAP, tune=None, stream=None):
     d = ds.as_c()
-    _check(lib().hd_decode_run(C.byref(d), _dev_ptr(out), mode, _tune_ptr(tune), _dev_ptr(workspace),
+    _check(lib().hd_decode_run(C.byref(d), _out_ptr(ds, out), mode, _tune_ptr(tune), _dev_ptr(workspace),
                                workspace.numel(), _stream_handle(stream)), "hd_decode_run")
 
 
@@ -337,7 +361,7 @@ def autotune(ds: DeviceStream, out, workspace=None, mode: int = MODE_GAP, stream
         workspace = alloc_workspace(decode_workspace_size(ds, mode), out.device)
     best = Tune()
     ms = C.c_float()
-    _check(lib().hd_autotune(C.byref(d), mode, _dev_ptr(out), _dev_ptr(workspace), workspace.numel(),
+    _check(lib().hd_autotune(C.byref(d), mode, _out_ptr(ds, out), _dev_ptr(workspace), workspace.numel(),
                              _stream_handle(stream), C.byref(best), C.byref(ms)), "hd_autotune")
     return best, float(ms.value)
 
@@ -368,6 +392,29 @@ def histogram(syms, A: int, hist=None, stream=None):
     _check(lib().hd_histogram(_dev_ptr(syms) if syms.numel() else None, syms.numel(), A, _dev_ptr(hist),
                               _stream_handle(stream)), "hd_histogram")
     return hist
+
+
+def build_codebook_device(hist, L: int, lengths=None, codes=None, workspace=None, stream=None):
+    """hd_build_codebook_device: (lengths uint8[A], codes int32[A], workspace) device tensors from an
+    int64 device histogram of A bins; the status bits are read with decode_status_bits(workspace)."""
+    import torch
+    A = hist.numel()
+    dev = hist.device
+    if lengths is None:
+        lengths = torch.empty(A, dtype=torch.uint8, device=dev)
+    if codes is None:
+        codes = torch.empty(A, dtype=torch.int32, device=dev)
+    if lengths.numel() < A or codes.numel() < A or lengths.element_size() != 1 or codes.element_size() != 4:
+        raise ValueError("lengths / codes must hold A uint8 / 32-bit entries")
+    if workspace is None:
+        nb = int(lib().hd_codebook_workspace_size(L))
+        if nb == 0:
+            raise HDError(ERR_ARG, "hd_codebook_workspace_size")
+        workspace = alloc_workspace(nb, dev)
+    _check(lib().hd_build_codebook_device(_dev_ptr(hist), A, L, _dev_ptr(lengths), _dev_ptr(codes),
+                                          _dev_ptr(workspace), workspace.numel(), _stream_handle(stream)),
+           "hd_build_codebook_device")
+    return lengths, codes, workspace
 
 
 @dataclass
@@ -448,6 +495,7 @@ def decode_status(workspace, stream=None) -> int:
 
 def decode_status_bits(workspace, stream=None) -> int:
     return int(lib().hd_decode_status_bits(_dev_ptr(workspace), _stream_handle(stream)))
+
 
 
 class Server:
