@@ -370,6 +370,26 @@ hd_status hd_decode_status(const void *workspace, void *hip_stream);
  */
 uint32_t hd_decode_status_bits(const void *workspace, void *hip_stream);
 
+/*
+ * hd_decode without a caller workspace and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The workspace is a
+ * fixed library array of HD_NOALLOC_SCRATCH_BYTES in device memory (one per
+ * GPU, held until the process ends, set up on the first call on each device);
+ * streams whose hd_decode_workspace_size exceeds it are refused with
+ * HD_ERR_UNSUPPORTED before anything is enqueued.  The call enqueues
+ * hd_decode's kernels on hip_stream, then writes the raw status bits (the
+ * value hd_decode_status_bits would return for a workspace) into *status, a
+ * caller-owned uint32 in device memory, with a plain store: no clearing
+ * needed, no host wait.  The array keeps the last call's contents; every
+ * word a call reads is written by that call first.  Calls that overlap on one
+ * GPU (different streams or threads without ordering) share the array and
+ * race: order them.  Same argument errors as hd_decode, plus HD_ERR_ARG for a
+ * NULL status.
+ */
+#define HD_NOALLOC_SCRATCH_BYTES (32u << 20)
+hd_status hd_decode_noalloc(const hd_dstream *s, void *out, hd_mode m, const hd_tune *tune,
+                            uint32_t *status, void *hip_stream);
 
 /* ------------------------------------------------------------ encoding -- */
 

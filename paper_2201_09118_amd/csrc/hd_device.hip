@@ -2984,3 +2984,91 @@ extern "C" hd_status hd_decode_status(const void *workspace, void *hip_stream)
     return v ? HD_ERR_CORRUPT : HD_OK;
 }
 
+// ------------------------------------------------------------------------
+// Allocation-free decode
+// ------------------------------------------------------------------------
+//
+// hd_decode with its workspace in a fixed device array.  Host code never
+// passes the array's name to a kernel: in host code the name is only a
+// stand-in for the symbol, so the device address of each GPU's copy is looked
+// up once (hipGetSymbolAddress, with that device current) and kept per device.
+
+namespace {
+
+constexpr size_t kScratchBytes = HD_NOALLOC_SCRATCH_BYTES;
+static_assert(kScratchBytes % 256 == 0, "scratch size");
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch[64];
+
+// The current device's copy of the array (nullptr when the lookup fails).
+void *scratch_of_current_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return nullptr;
+        g_scratch[dev] = p;
+    }
+    return g_scratch[dev];
+}
+
+// One workgroup: the status word of a decode workspace, header word 0 OR the
+// slots the last decode kernel wrote (word 1 counts them), stored to *out.
+__global__ __launch_bounds__(256) void k_fold_status(const uint32_t *ws, uint32_t *out)
+{
+    __shared__ uint32_t acc[4];
+    const uint32_t ns = ws[1];
+    uint32_t v = 0;
+    if (ns > kMaxSlots) {
+        v = 0xffffffffu;                              // an unreadable status
+    } else {
+        const uint32_t *slots = ws + kWsHeader / 4;
+        for (uint32_t i = threadIdx.x; i < ns; i += blockDim.x)
+            v |= slots[i];
+        if (threadIdx.x == 0)
+            v |= ws[0];
+    }
+    v = wave_or(v);
+    if ((threadIdx.x & 63) == 0)
+        acc[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t r = acc[0] | acc[1] | acc[2] | acc[3];
+        // all ones means "unreadable"; status bits alone never reach bit 31
+        *out = ns > kMaxSlots ? r : (r & 0x7fffffffu);
+    }
+}
+
+}  // namespace
+
+extern "C" hd_status hd_decode_noalloc(const hd_dstream *s, void *out, hd_mode m, const hd_tune *tune,
+                                       uint32_t *status, void *hip_stream)
+{
+    hd_status st = check_stream(s, m);
+    if (st != HD_OK)
+        return st;
+    if (!status || reinterpret_cast<uintptr_t>(status) % 4 != 0)
+        return HD_ERR_ARG;
+    size_t need = 0;
+    st = hd_decode_workspace_size(s, m, tune, &need);
+    if (st != HD_OK)
+        return st;
+    if (need > kScratchBytes)
+        return HD_ERR_UNSUPPORTED;
+    void *ws = scratch_of_current_device();
+    if (!ws)
+        return HD_ERR_DEVICE;
+    st = hd_decode(s, out, m, tune, ws, kScratchBytes, hip_stream);
+    if (st != HD_OK)
+        return st;
+    hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                       static_cast<const uint32_t *>(ws), status);
+    return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
+}

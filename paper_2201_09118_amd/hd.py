@@ -42,6 +42,7 @@ SIGNATURES = {
     "hd_decode_cr_classes": (C.c_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
     "hd_decode_status": (C.c_int, [_vp, _vp]),
     "hd_decode_status_bits": (_u32, [_vp, _vp]),
+    "hd_decode_noalloc": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp, _vp]),
     "hd_lorenzo_workspace_size": (_sz, [_u32, _u32, _u32]),
     "hd_histogram": (C.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "hd_codebook_workspace_size": (_sz, [_u32]),
@@ -496,6 +497,16 @@ def decode_status(workspace, stream=None) -> int:
 def decode_status_bits(workspace, stream=None) -> int:
     return int(lib().hd_decode_status_bits(_dev_ptr(workspace), _stream_handle(stream)))
 
+
+NOALLOC_SCRATCH_BYTES = 32 << 20   # HD_NOALLOC_SCRATCH_BYTES
+
+
+def decode_noalloc(ds: DeviceStream, out, status, mode: int = MODE_GAP, tune=None, stream=None):
+    """Enqueues hd_decode_noalloc; status is a one-element int32/uint32 device tensor that
+    receives the raw status bits."""
+    d = ds.as_c()
+    _check(lib().hd_decode_noalloc(C.byref(d), _out_ptr(ds, out), mode, _tune_ptr(tune), _dev_ptr(status),
+                                   _stream_handle(stream)), "hd_decode_noalloc")
 
 
 class Server:

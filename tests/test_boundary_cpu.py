@@ -214,3 +214,11 @@ def test_stream_layout_sizes_match_the_encoders():
         assert ei.value.status == st
     with pytest.raises(hd.HDError):
         hd.stream_layout(10, 20, 4, 4, 48, 1)
+
+
+def test_noalloc_scratch_size_matches_header():
+    from paper_2201_09118_amd import hd
+    txt = open(os.path.join(ROOT, "include", "hd.h")).read()
+    m = re.search(r"#define HD_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", txt)
+    assert m, "HD_NOALLOC_SCRATCH_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == hd.NOALLOC_SCRATCH_BYTES
