@@ -34,15 +34,35 @@ SZ_PROFILE = os.path.join(ROOT, "profiles", "sz_reconstruct_config2.md")
 SZ_SRC = os.path.join(ROOT, "paper_2201_09118_amd", "csrc", "hd_lorenzo.hip")
 
 
-def measured_traffic(profile=PROFILE, kernel_src=KERNEL_SRC):
+GAP_KERNEL_SECTIONS = (("", "// Self-synchronization (Sec. III-B-2"),
+                       ("// Host entry points", "// Algorithm 2 host side"))
+
+
+def kernel_source_digest(kernel_src=KERNEL_SRC, sections=None):
+    """sha256 of the source the gap-mode decode kernel is built and launched
+    from: the decode table, device primitives and decode kernels (the file up
+    to the self-synchronization section) and the host section that plans and
+    launches it.  The self-sync, batch and other sections do not enter it."""
+    import hashlib
+    text = open(kernel_src).read()
+    h = hashlib.sha256()
+    if sections is None:                 # the whole file
+        h.update(text.encode())
+        return h.hexdigest()
+    for begin, end in sections:
+        i = text.index(begin) if begin else 0
+        h.update(text[i:text.index(end, i)].encode())
+    return h.hexdigest()
+
+
+def measured_traffic(profile=PROFILE, kernel_src=KERNEL_SRC, sections=GAP_KERNEL_SECTIONS):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or
     None when the kernel source changed since it was taken."""
-    import hashlib
     import re
     try:
         txt = open(profile).read()
-        src = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    except OSError:
+        src = kernel_source_digest(kernel_src, sections)
+    except (OSError, ValueError):
         return None
     m = re.search(r"traffic_bytes_per_launch: (\d+) \(kernel source sha256 ([0-9a-f]{64})\)", txt)
     if not m or m.group(2) != src:
@@ -533,7 +553,7 @@ def bench_sz(args):
                                                     "radius 512; codes Huffman-coded with A=1024, L=24, S=128, C=32",
                    "n": n, "outliers": int(F.outlier_idx.size), "n_bits": hs.n_bits},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(SZ_PROFILE, SZ_SRC),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(SZ_PROFILE, SZ_SRC, None),
                      "kernel": "hd_lorenzo_reconstruct (k_lz_plane_ring + k_lz_carry + k_lz_depth)",
                      "kernel_ms": round(rec_ms, 5), "alg_bytes_per_launch": alg},
         "stages_ms": {"decode": round(dec_ms, 5), "reconstruct": round(rec_ms, 5)},
@@ -1093,7 +1113,10 @@ def batch_measure(args):
                    "sizes": [args.batch_lo, args.batch_hi], "alphabets": [256, 1024, 4096], "max_len": 24},
         "batched_speedup": round(t_plain / t_batch, 3),
         "plain_back_to_back": {"ms": round(t_plain, 4), "gbs": round(g_plain, 2)},
-        "batched": {"ms": round(t_batch, 4), "gbs": round(g_batch, 2), "launches": 1,
+        # streams of 2^22 symbols or more take their own decode launch inside the batch call
+        "batched": {"ms": round(t_batch, 4), "gbs": round(g_batch, 2),
+                    "launches": int(sum(x.size >= (1 << 22) for x in xs)) + int(any(x.size < (1 << 22) for x in xs)),
+                    "solo_streams": int(sum(x.size >= (1 << 22) for x in xs)),
                     "shape": {"waves_per_group": btunes[0].waves_per_group or "occupancy",
                               "stage_cap": max(t.stage_symbols for t in btunes)}},
         "launch_shape_sweep_ms": shape_ms,

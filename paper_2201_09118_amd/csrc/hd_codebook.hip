@@ -50,10 +50,13 @@ constexpr size_t kCbLevelWords = kCbMaxUsed + 2;
 constexpr size_t cb_ws_bytes(uint32_t L) { return kCbHead + size_t(L + 1) * kCbLevelWords * 4; }
 
 // LDS: sorted keys (32 KB) + two pair buffers (2 x 32 KB, later the 64 KB
-// length map) + small counters.
+// length map) + the per-level pair counts as uint16 when they fit (56 KB:
+// (L + 1) (m + 2) entries; larger codes keep them in the global workspace)
+// + small counters.
 constexpr size_t kCbKeysBytes = size_t(kCbMaxUsed) * 8;
 constexpr size_t kCbPairBytes = size_t(kCbMaxUsed) * 8;
-constexpr size_t kCbLdsBytes = kCbKeysBytes + 2 * kCbPairBytes;
+constexpr size_t kCbLevelLdsBytes = 56 * 1024;
+constexpr size_t kCbLdsBytes = kCbKeysBytes + 2 * kCbPairBytes + kCbLevelLdsBytes;
 
 struct CbShared {
     uint32_t n_used;
@@ -99,6 +102,7 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(const uint64_t *__restr
     uint64_t *const pb0 = reinterpret_cast<uint64_t *>(smem + kCbKeysBytes);
     uint64_t *const pb1 = reinterpret_cast<uint64_t *>(smem + kCbKeysBytes + kCbPairBytes);
     uint8_t *lmap = smem + kCbKeysBytes;                  // after the levels: length per symbol
+    uint16_t *lev16 = reinterpret_cast<uint16_t *>(smem + kCbKeysBytes + 2 * kCbPairBytes);
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
 
     if (tid == 0) {
@@ -165,7 +169,12 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(const uint64_t *__restr
         }
     }
 
-    // 2. levels.  Pairs of level L (the ranked symbols themselves):
+    // 2. levels.  The pair counts of level d go to lev16[d * (m + 2) ...] when
+    // every level fits (one LDS read per level in the selection below),
+    // else to the global workspace.
+    const uint32_t lstride = m + 2;
+    const bool lev_in_lds = size_t(L + 1) * lstride * 2 <= kCbLevelLdsBytes;
+    // Pairs of level L (the ranked symbols themselves):
     uint32_t np = m >> 1;
     for (uint32_t k = tid; k < np; k += kCbThreads)
         pb0[k] = (keys[2 * k] >> 24) + (keys[2 * k + 1] >> 24);
@@ -177,6 +186,7 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(const uint64_t *__restr
         const uint64_t *P = cur ? pb1 : pb0;
         uint64_t *Q = cur ? pb0 : pb1;
         uint32_t *pp = levels + size_t(d) * kCbLevelWords;
+        uint16_t *pl = lev16 + size_t(d) * lstride;
         const uint32_t T = m + np;                      // items of level d
         const uint32_t slots = (T + 1) >> 1;            // pair slots (the last may hold one item)
         const uint32_t per = (slots + kCbThreads - 1) / kCbThreads;
@@ -185,7 +195,10 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(const uint64_t *__restr
             uint32_t i = merge_split(keys, m, P, np, 2 * k0);
             uint32_t j = 2 * k0 - i;
             for (uint32_t k = k0; k < k1; ++k) {
-                pp[k] = j;                              // pairs among the first 2k items
+                if (lev_in_lds)                         // pairs among the first 2k items
+                    pl[k] = static_cast<uint16_t>(j);
+                else
+                    pp[k] = j;
                 uint64_t v[2] = {0, 0};
                 for (uint32_t h = 0; h < 2 && 2 * k + h < T; ++h) {
                     if (i < m && (j >= np || (keys[i] >> 24) <= P[j]))
@@ -197,8 +210,12 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(const uint64_t *__restr
                     Q[k] = v[0] + v[1];
             }
         }
-        if (tid == 0 && (T & 1u) == 0)
-            pp[T >> 1] = np;                            // the whole level
+        if (tid == 0 && (T & 1u) == 0) {                // the whole level
+            if (lev_in_lds)
+                pl[T >> 1] = static_cast<uint16_t>(np);
+            else
+                pp[T >> 1] = np;
+        }
         np = T >> 1;
         cur ^= 1;
         __syncthreads();
@@ -214,7 +231,9 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(const uint64_t *__restr
                 sh.singles[d] = take;                   // level L holds symbols only
                 break;
             }
-            const uint32_t pairs = __builtin_nontemporal_load(levels + size_t(d) * kCbLevelWords + (take >> 1));
+            const uint32_t pairs = lev_in_lds ? lev16[size_t(d) * lstride + (take >> 1)]
+                                              : __builtin_nontemporal_load(levels + size_t(d) * kCbLevelWords +
+                                                                           (take >> 1));
             sh.singles[d] = take - pairs;
             take = 2 * pairs;
             if (take == 0) {

@@ -2242,7 +2242,7 @@ namespace {
 // The decode-and-write launch of a checked call.  direct: a caller-zeroed
 // status word (gap mode only; the workspace is then not used).
 hd_status run_decode_kernel(const hd_dstream *s, void *out, hd_mode m, const hd_tune *tune, void *workspace,
-                            uint32_t *direct, hipStream_t stream)
+                            uint32_t *direct, hipStream_t stream, bool direct_atomic = false)
 {
     hd_status st = HD_OK;
     const hd_stream_info &i = s->info;
@@ -2272,7 +2272,7 @@ hd_status run_decode_kernel(const hd_dstream *s, void *out, hd_mode m, const hd_
     a.slots = w.slots;
     a.own_head = ss ? 0u : 1u;
     a.direct = direct;
-    a.direct_atomic = 0;
+    a.direct_atomic = direct_atomic ? 1u : 0u;
     a.list = nullptr;
     a.n_list = 0;
     a.tab = view_of(s->table);
@@ -2700,6 +2700,10 @@ extern "C" hd_status hd_decode_batch_workspace_size(const hd_dstream *streams, u
 
 namespace {
 
+// Batched decode: streams of at least this many symbols get their own decode
+// launch (a persistent grid of the single-stream kernel is then mostly full).
+constexpr uint64_t kBatchSoloSymbols = uint64_t(1) << 22;
+
 hd_status decode_batch_impl(const hd_dstream *streams, uint32_t n_streams, uint16_t *const *outs, hd_mode m,
                             const hd_tune *per_stream, void *workspace, size_t ws_bytes, void *hip_stream,
                             uint32_t *direct)
@@ -2724,13 +2728,17 @@ hd_status decode_batch_impl(const hd_dstream *streams, uint32_t n_streams, uint1
     char *ws = static_cast<char *>(workspace);
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
 
-    // one launch for the whole batch: the LDS layout reserves the largest
-    // table, subsequence and staging of the batch; waves per workgroup and
-    // workgroups per CU come from per_stream[0] (zero: the most resident
-    // wavefronts that layout allows)
+    // Streams of at least kBatchSoloSymbols fill the device on their own:
+    // each gets the single-stream decode launch with its own plan (table
+    // format, registers, staging and occupancy of that stream), enqueued
+    // first.  The rest share one persistent launch, whose LDS layout reserves
+    // the largest table, subsequence and staging among them; its waves per
+    // workgroup and workgroups per CU come from per_stream[0] (zero: the most
+    // resident wavefronts that layout allows).
     uint32_t S_alloc = 32, stage_alloc = 256, k1_alloc = 1, n_pair = 0, auto_max = 0;
     std::vector<uint32_t> stage(n_streams);
     std::vector<bool> given(n_streams);
+    std::vector<uint32_t> shared, solo;
     for (uint32_t i = 0; i < n_streams; ++i) {
         const hd_stream_info &si = streams[i].info;
         const hd_tune *tu = per_stream ? &per_stream[i] : nullptr;
@@ -2738,13 +2746,18 @@ hd_status decode_batch_impl(const hd_dstream *streams, uint32_t n_streams, uint1
         stage[i] = given[i] ? tu->stage_symbols : auto_stage_for(si);
         if (stage[i] < 256 || stage[i] > 16384 || stage[i] % 64)
             return HD_ERR_ARG;
-        if (!given[i])
-            auto_max = std::max(auto_max, stage[i]);
         if ((si.n_symbols && !outs[i]) || reinterpret_cast<uintptr_t>(outs[i]) % 16 ||
             reinterpret_cast<uintptr_t>(streams[i].words) % 16)
             return HD_ERR_ARG;
         if (64 % si.chunk_subseqs)
             return HD_ERR_UNSUPPORTED;
+        if (si.n_symbols >= kBatchSoloSymbols) {
+            solo.push_back(i);
+            continue;
+        }
+        shared.push_back(i);
+        if (!given[i])
+            auto_max = std::max(auto_max, stage[i]);
         S_alloc = std::max(S_alloc, si.subseq_bits);
         if (given[i])
             stage_alloc = std::max(stage_alloc, stage[i]);
@@ -2758,7 +2771,7 @@ hd_status decode_batch_impl(const hd_dstream *streams, uint32_t n_streams, uint1
         // need (streams above the cap decode their larger tiles in passes)
         std::vector<std::pair<uint32_t, uint64_t>> need;
         uint64_t total = 0;
-        for (uint32_t i = 0; i < n_streams; ++i)
+        for (uint32_t i : shared)
             if (!given[i]) {
                 need.emplace_back(stage[i], streams[i].info.n_symbols);
                 total += streams[i].info.n_symbols;
@@ -2773,14 +2786,15 @@ hd_status decode_batch_impl(const hd_dstream *streams, uint32_t n_streams, uint1
             }
         const uint32_t cap = std::max(median, stage_for_waves(table_lds_bytes(k1_alloc), S_alloc, 16, dev));
         const uint32_t use = std::min(auto_max, cap);
-        for (uint32_t i = 0; i < n_streams; ++i)
+        for (uint32_t i : shared)
             if (!given[i])
                 stage[i] = std::min(stage[i], use);
         stage_alloc = std::max(stage_alloc, use);
     }
+    const uint32_t n_shared = static_cast<uint32_t>(shared.size());
     const uint32_t table = table_lds_bytes(k1_alloc), area = wave_area_bytes(S_alloc, stage_alloc);
     const hd_tune *t0 = per_stream ? &per_stream[0] : nullptr;
-    const int formats = n_pair == n_streams ? kBatchPairOnly : n_pair == 0 ? kBatchWideOnly : kBatchMixed;
+    const int formats = n_pair == n_shared ? kBatchPairOnly : n_pair == 0 ? kBatchWideOnly : kBatchMixed;
     const bool small = S_alloc <= 32 * kSmallUnits;
     const void *func = batch_kernel(formats, small);
     const uint32_t reg_cap = reg_waves_per_cu(func);
@@ -2801,12 +2815,13 @@ hd_status decode_batch_impl(const hd_dstream *streams, uint32_t n_streams, uint1
     if (t0 && t0->groups_per_cu)
         fit = std::min(fit, t0->groups_per_cu);
 
-    std::vector<BatchStreamDev> d(n_streams);
+    std::vector<BatchStreamDev> d(n_shared);
     uint64_t items = 0;
-    for (uint32_t i = 0; i < n_streams; ++i) {
+    for (uint32_t q = 0; q < n_shared; ++q) {
+        const uint32_t i = shared[q];
         const hd_dstream &s = streams[i];
         const hd_stream_info &si = s.info;
-        BatchStreamDev &b = d[i];
+        BatchStreamDev &b = d[q];
         b.sd.words = s.words;
         b.sd.gap = s.gap;
         b.sd.chunk_off = s.chunk_offsets;
@@ -2836,7 +2851,7 @@ hd_status decode_batch_impl(const hd_dstream *streams, uint32_t n_streams, uint1
         return HD_ERR_NOMEM;
     char *h = static_cast<char *>(sb->host);
     std::memset(h, 0, up);
-    std::memcpy(h + L.desc, d.data(), sizeof(BatchStreamDev) * n_streams);
+    std::memcpy(h + L.desc, d.data(), sizeof(BatchStreamDev) * n_shared);
     if (hipMemcpyAsync(ws, h, up, hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipEventRecord(sb->done, stream) != hipSuccess) {
         std::lock_guard<std::mutex> lk(g_stage_mu);
@@ -2844,11 +2859,23 @@ hd_status decode_batch_impl(const hd_dstream *streams, uint32_t n_streams, uint1
         return HD_ERR_DEVICE;
     }
     uint32_t *status = reinterpret_cast<uint32_t *>(ws);
+    // the large streams, after the upload that zeroes the status word: each
+    // wavefront that met an error ORs its bits into that word (or, for the
+    // server, stores them into its pinned word)
+    for (uint32_t i : solo) {
+        hd_tune tu{};
+        if (given[i])
+            tu.stage_symbols = stage[i];
+        st = run_decode_kernel(&streams[i], outs[i], HD_MODE_GAP, given[i] ? &tu : nullptr, nullptr,
+                               direct ? direct : status, stream, direct == nullptr);
+        if (st != HD_OK)
+            return st;
+    }
     if (items == 0)
         return HD_OK;
     BatchArgs a;
     a.streams = reinterpret_cast<const BatchStreamDev *>(ws + L.desc);
-    a.n_streams = n_streams;
+    a.n_streams = n_shared;
     a.n_items = items;
     a.status = direct ? direct : status;
     a.direct = direct ? 1u : 0u;

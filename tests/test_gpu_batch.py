@@ -149,3 +149,42 @@ def test_autotuned_batch_launch_shape_decodes_exactly():
         assert np.array_equal(o[:c.x.size].cpu().numpy().view(np.uint16), expected(c))
     again, _ = tuner.batch_launch(dss, outs, tunes, ws, keys)       # cached
     assert [t.waves_per_group for t in again] == [t.waves_per_group for t in shaped]
+
+
+def test_batch_with_streams_above_the_solo_threshold():
+    """Streams of 2^22 symbols and more get their own decode launch inside
+    hd_decode_batch; they are interleaved here with small streams (shared
+    persistent launch), with per-stream staging given for some of them, and
+    every output must equal the oracle's and the single-stream decode's."""
+    rng = np.random.default_rng(47)
+    sizes = [(1 << 22) + 5, 3000, (1 << 22) + 70_001, 17, 250_000, 5_000_000]
+    cases = []
+    for i, n in enumerate(sizes):
+        A = [1024, 256, 4096, 2, 20000, 1024][i]
+        x = hdsynth.two_sided_geometric(rng, n, float(rng.uniform(0.3, 0.8)), A)
+        used = int((np.bincount(x, minlength=A) > 0).sum())
+        L = max(int(np.ceil(np.log2(max(used, 2)))), 20)
+        cases.append(make_case(x, A, L, [128, 64, 256, 128, 128, 64][i], [32, 8, 32, 1, 64, 64][i]))
+    for tunes in (None, [{"stage_symbols": [0, 512, 2048, 0, 1024, 4096][i]} for i in range(len(cases))]):
+        flush(f"batch with large streams, tunes={tunes is not None}")
+        dss, got, bits = _run_batch(cases, tunes)
+        assert bits == 0, f"status {bits:#x}"
+        for c, g, ds in zip(cases, got, dss):
+            assert np.array_equal(g, expected(c))
+
+
+def test_batch_reports_a_fault_in_a_large_stream():
+    """A gap byte off by one in a stream above the solo threshold: the batch's
+    status word must carry the fault although that stream ran in its own launch."""
+    rng = np.random.default_rng(48)
+    big = make_case(hdsynth.two_sided_geometric(rng, (1 << 22) + 9, 0.6, 1024), 1024, 20, 128, 32)
+    small = make_case(hdsynth.two_sided_geometric(rng, 30_000, 0.6, 1024), 1024, 20, 128, 32)
+    import torch
+    from paper_2201_09118_amd import hd
+    dss = [upload(big), upload(small)]
+    dss[0].gap[1000] += 1
+    outs = [torch.zeros(c.x.size + 64, dtype=torch.int16, device="cuda") for c in (big, small)]
+    ws = hd.decode_batch(dss, outs, hd.MODE_GAP)
+    bits = hd.decode_status_bits(ws)
+    assert bits != 0
+    assert np.array_equal(outs[1][:small.x.size].cpu().numpy().view(np.uint16), expected(small))
