@@ -1113,10 +1113,10 @@ def batch_measure(args):
                    "sizes": [args.batch_lo, args.batch_hi], "alphabets": [256, 1024, 4096], "max_len": 24},
         "batched_speedup": round(t_plain / t_batch, 3),
         "plain_back_to_back": {"ms": round(t_plain, 4), "gbs": round(g_plain, 2)},
-        # streams of 2^22 symbols or more take their own decode launch inside the batch call
+        # streams of 2^23 symbols or more take their own decode launch inside the batch call
         "batched": {"ms": round(t_batch, 4), "gbs": round(g_batch, 2),
-                    "launches": int(sum(x.size >= (1 << 22) for x in xs)) + int(any(x.size < (1 << 22) for x in xs)),
-                    "solo_streams": int(sum(x.size >= (1 << 22) for x in xs)),
+                    "launches": int(sum(x.size >= (1 << 23) for x in xs)) + int(any(x.size < (1 << 23) for x in xs)),
+                    "solo_streams": int(sum(x.size >= (1 << 23) for x in xs)),
                     "shape": {"waves_per_group": btunes[0].waves_per_group or "occupancy",
                               "stage_cap": max(t.stage_symbols for t in btunes)}},
         "launch_shape_sweep_ms": shape_ms,

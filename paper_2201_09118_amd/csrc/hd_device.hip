@@ -1083,10 +1083,20 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
     }
 }
 
-// Iterations whose entries the count pass logs per lane (pair format): 24
-// registers; enough for nearly every lane at S = 128, and at larger S the
-// rest of a lane is walked.
+// Iterations whose entries the count pass logs per lane (pair format), two
+// registers each.  At S <= 128 (about 22 codewords per lane at 6 bits) a
+// lane needs some 6-8 iterations; a longer log costs registers and so
+// occupancy, and lanes past the log finish by walking.  At larger S most
+// lanes walk past the log anyway.
+constexpr int kLogItersSmall = 8;
 constexpr int kLogIters = 12;
+// Entry-log length of the decode kernel for subsequences of at most
+// 32 * MAXU bits.
+template <uint32_t MAXU>
+constexpr int log_iters()
+{
+    return MAXU <= kSmallUnits ? kLogItersSmall : kLogIters;
+}
 
 template <bool PAIR, uint32_t MAXU, bool LISTED = false, typename T = uint16_t>
 __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
@@ -1134,7 +1144,7 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
         const uint64_t tn = tile_at(i + tstride);
         in.load(sd, tn, ntiles, lane);
         wave_lds_sync();
-        decode_tile<PAIR, PAIR ? kLogIters : 0>(sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, g, sh,
+        decode_tile<PAIR, PAIR ? log_iters<MAXU>() : 0>(sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, g, sh,
                                                 err);
         t = tn;
     }
@@ -1735,7 +1745,7 @@ __global__ __launch_bounds__(1024) void k_decode_batch(BatchArgs a)
             const SmemTable st = carve_table(smem, bs.tab.k1);
             const uint32_t sh = 32 - bs.tab.k1;
             if (FORMATS == kBatchPairOnly || (FORMATS == kBatchMixed && bs.pair))
-                decode_tile<true, MAXU == kSmallUnits ? kLogIters : 0>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl,
+                decode_tile<true, MAXU == kSmallUnits ? kLogItersSmall : 0>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl,
                                                                        stage, dummy, st, bs.tab, sh, err);
             else
                 decode_tile<false, 0>(bs.sd, t, lane, gk, gn, c_lo, c_hi, TTl, stage, dummy, st, bs.tab, sh, err);
@@ -2702,7 +2712,7 @@ namespace {
 
 // Batched decode: streams of at least this many symbols get their own decode
 // launch (a persistent grid of the single-stream kernel is then mostly full).
-constexpr uint64_t kBatchSoloSymbols = uint64_t(1) << 22;
+constexpr uint64_t kBatchSoloSymbols = uint64_t(1) << 23;
 
 hd_status decode_batch_impl(const hd_dstream *streams, uint32_t n_streams, uint16_t *const *outs, hd_mode m,
                             const hd_tune *per_stream, void *workspace, size_t ws_bytes, void *hip_stream,

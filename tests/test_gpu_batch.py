@@ -152,12 +152,12 @@ def test_autotuned_batch_launch_shape_decodes_exactly():
 
 
 def test_batch_with_streams_above_the_solo_threshold():
-    """Streams of 2^22 symbols and more get their own decode launch inside
+    """Streams of 2^23 symbols and more get their own decode launch inside
     hd_decode_batch; they are interleaved here with small streams (shared
     persistent launch), with per-stream staging given for some of them, and
     every output must equal the oracle's and the single-stream decode's."""
     rng = np.random.default_rng(47)
-    sizes = [(1 << 22) + 5, 3000, (1 << 22) + 70_001, 17, 250_000, 5_000_000]
+    sizes = [(1 << 23) + 5, 3000, (1 << 23) + 70_001, 17, 250_000, 5_000_000]
     cases = []
     for i, n in enumerate(sizes):
         A = [1024, 256, 4096, 2, 20000, 1024][i]
@@ -177,7 +177,7 @@ def test_batch_reports_a_fault_in_a_large_stream():
     """A gap byte off by one in a stream above the solo threshold: the batch's
     status word must carry the fault although that stream ran in its own launch."""
     rng = np.random.default_rng(48)
-    big = make_case(hdsynth.two_sided_geometric(rng, (1 << 22) + 9, 0.6, 1024), 1024, 20, 128, 32)
+    big = make_case(hdsynth.two_sided_geometric(rng, (1 << 23) + 9, 0.6, 1024), 1024, 20, 128, 32)
     small = make_case(hdsynth.two_sided_geometric(rng, 30_000, 0.6, 1024), 1024, 20, 128, 32)
     import torch
     from paper_2201_09118_amd import hd
