@@ -816,6 +816,17 @@ __device__ __forceinline__ uint32_t *tt_of(unsigned char *area, int lane)
     return reinterpret_cast<uint32_t *>(area) - 64 + lane;
 }
 
+// Lanes of a tile the entry probe of the self-sync kernel follows at most.
+constexpr uint32_t kProbeLanes = 4;
+
+// A sync-kernel wavefront's LDS: the transposed units, then the first
+// kProbeLanes lanes' units of both tiles of a pair (the probe's inputs) and
+// the two tiles' step-1 results (TileSync, 12 bytes each).
+__host__ __device__ __forceinline__ uint32_t sync_wave_bytes(uint32_t S)
+{
+    return wave_units_bytes(S) + 4 * 2 * kProbeLanes * ((S >> 5) + 1) + 32;
+}
+
 __host__ __device__ __forceinline__ uint32_t wave_area_bytes(uint32_t S, uint32_t stage, uint32_t sym_bytes = 2)
 {
     return wave_units_bytes(S) + sym_bytes * (stage + 64);
@@ -1086,10 +1097,11 @@ __device__ __forceinline__ void decode_tile(const StreamDev &sd, uint64_t t, int
 // Iterations whose entries the count pass logs per lane (pair format), two
 // registers each.  At S <= 128 (about 22 codewords per lane at 6 bits) a
 // lane needs some 6-8 iterations; a longer log costs registers and so
-// occupancy, and lanes past the log finish by walking.  At larger S most
-// lanes walk past the log anyway.
+// occupancy, and lanes past the log finish by walking.  At S = 256 (some 30
+// codewords per lane at 8 bits) the kernel holds four wavefronts per SIMD
+// from 12 to 28 iterations, and a log that covers most lanes pays.
 constexpr int kLogItersSmall = 8;
-constexpr int kLogIters = 12;
+constexpr int kLogIters = 18;
 // Entry-log length of the decode kernel for subsequences of at most
 // 32 * MAXU bits.
 template <uint32_t MAXU>
@@ -1195,20 +1207,23 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 // chained from lane 0), so no budget ever decides the result.
 //
 // Step 2 (inter-tile): the entry of tile u is the exit of tile u-1's last
-// lane.  Phase 1 assumes entry 0 and then walks lane 0's subsequence from
-// every entry g < L; if all of them leave at the same exit, the tile is
-// entry-independent: only lane 0's start and count depend on the true entry
-// (the count per entry is recorded).  The link kernel fixes lane 0 of every
-// tile whose predecessor's exit is final, and re-syncs, in order, runs of
-// entry-dependent tiles (codes that never resynchronize end up here).
+// lane.  Phase 1 assumes entry 0 and then walks the tile's first lanes from
+// every entry g < L, lane after lane, until all entries leave a lane j at the
+// same exit (at most kProbeLanes lanes): then only lanes 0..j depend on the
+// true entry (their starts and summed count per entry are recorded) and the
+// tile's later paths and last exit do not.  The link kernel fixes lanes
+// 0..j of every tile whose predecessor's exit is final, and re-syncs, in
+// order, runs of tiles whose entries did not converge within the probe
+// (codes that never resynchronize end up here).
 
-constexpr uint32_t kSyncRecBytes = 72;
+constexpr uint32_t kSyncRecBytes = 168;
 
 struct SyncRec {
-    uint8_t last_entry;       // next tile's lane-0 start implied by this tile's path
-    uint8_t indep;            // lane 0's exit is the same for every entry < L
+    uint8_t last_entry;       // next tile's lane-0 start implied by this tile's paths
+    uint8_t dep;              // lanes 0 .. dep-1 depend on the entry; 0: the probe found no common exit
     uint8_t pad[6];
-    uint16_t count_at[32];    // lane 0's codeword count from entry g
+    uint16_t count_at[32];    // codewords of lanes 0 .. dep-1 from entry g
+    uint8_t start_at[kProbeLanes - 1][32];   // start of lane i + 1 (< dep) from entry g
 };
 static_assert(sizeof(SyncRec) == kSyncRecBytes, "record layout");
 
@@ -1329,12 +1344,18 @@ __device__ __forceinline__ uint32_t lane_end(uint64_t k, uint64_t K, uint64_t B,
     return k + 1 == K ? static_cast<uint32_t>(B - k * S) : S;
 }
 
-// Runs step 1 on tile t, stores its sync points and codeword total, and
-// returns the next tile's entry implied by the tile's last exit.
+// The tile's totals after step 1 (wavefront-uniform).
+struct TileSync {
+    uint32_t total, last_exit;    // codewords of the tile; its last lane's exit
+    bool done;                    // the rounds converged
+    bool off_end;                 // the stream's last subsequence (in this tile) ends off the stream end
+};
+
+// Runs step 1 on tile t (lane 0 starting at e0), stores the sync points and,
+// when the rounds do not converge within max_rounds, lists the tile.
 template <bool PAIR>
-__device__ uint32_t sync_and_store(const SyncArgs &a, uint64_t t, uint32_t *TTl, int lane, uint32_t e0,
-                                   bool with_record, uint32_t max_rounds, const SmemTable &st,
-                                   const TableView &g, uint32_t sh)
+__device__ TileSync sync_core(const SyncArgs &a, uint64_t t, const uint32_t *TTl, int lane, uint32_t e0,
+                              uint32_t max_rounds, const SmemTable &st, const TableView &g, uint32_t sh)
 {
     const uint32_t S = a.S;
     const uint64_t k = (t << 6) + lane;
@@ -1351,57 +1372,113 @@ __device__ uint32_t sync_and_store(const SyncArgs &a, uint64_t t, uint32_t *TTl,
         a.pending[atomicAdd(a.n_pending, 1u)] = static_cast<uint32_t>(t);
     if (act)
         a.gap_s[k] = static_cast<uint8_t>(start);
-    const uint32_t total = static_cast<uint32_t>(wave_sum_u64(cnt));
-    const uint32_t last_exit = __shfl(exit, 63, 64);
-    if (with_record) {
-        // entry independence of lane 0: walk its subsequence from every entry.
-        // Every lane first copies lane 0's units into its own column (reads
-        // of one address are broadcast), so the probe walks conflict-free.
-        wave_lds_sync();
-        {
-            const uint32_t *c0 = TTl - lane;
-            for (uint32_t w = 1; w <= (S >> 5) + 1; ++w)
-                TTl[w * 64] = c0[w * 64];
-        }
-        wave_lds_sync();
-        const uint32_t *TT0 = TTl;
-        const uint32_t st0 = __shfl(start, 0, 64), ex0 = __shfl(exit, 0, 64);
-        const uint32_t cn0 = __shfl(cnt, 0, 64), E0 = __shfl(E, 0, 64);
-        uint32_t exg = ex0, cng = cn0;
-        const bool probe = lane < static_cast<int>(g.L);
-        // a full walk per entry (two groups per window read): stepping each
-        // entry's path against lane 0's one codeword at a time until they
-        // meet measured slower (sync kernel 260 vs 201 us on 134 M symbols)
-        if (probe && static_cast<uint32_t>(lane) != st0)
-            run_path<PAIR>(TT0, lane, E0, st, g, sh, exg, cng);
-        const bool differs = probe && exg != ex0;
-        const bool indep = __builtin_amdgcn_ballot_w64(differs) == 0;
-        // the tile's paths are final when its entry is (tile 0) or does not
-        // matter, and the rounds converged; otherwise a later kernel decides
-        if (off_end && done && (t == 0 || indep))
+    TileSync r;
+    r.total = static_cast<uint32_t>(wave_sum_u64(cnt));
+    r.last_exit = __shfl(exit, 63, 64);
+    r.done = done;
+    r.off_end = __builtin_amdgcn_ballot_w64(off_end) != 0;
+    return r;
+}
+
+// Re-syncs tile t from its true entry e0 with enough rounds (the link step)
+// and stores its total; returns the next tile's entry.
+template <bool PAIR>
+__device__ uint32_t resync_tile(const SyncArgs &a, uint64_t t, const uint32_t *TTl, int lane, uint32_t e0,
+                                const SmemTable &st, const TableView &g, uint32_t sh)
+{
+    const TileSync r = sync_core<PAIR>(a, t, TTl, lane, e0, kMaxRounds, st, g, sh);
+    if (lane == 0) {
+        if (r.off_end)
             atomicOr(a.status, kErrNoSync);
-        SyncRec *r = a.rec + t;
-        if (lane < 32)
-            r->count_at[lane] = static_cast<uint16_t>(probe ? cng : 0u);
-        if (lane == 0) {
-            r->last_entry = static_cast<uint8_t>(last_exit - S);
-            r->indep = indep ? 1 : 0;
-            a.tot[t] = total;
+        a.tot[t] = r.total;
+        a.rec[t].last_entry = static_cast<uint8_t>(r.last_exit - a.S);
+    }
+    return r.last_exit - a.S;
+}
+
+// The entry probe of two tiles in one pass: lanes 0..31 follow tile t0 from
+// entries 0..31, lanes 32..63 tile t1 (entries from L on are not followed).
+// Each lane walks the tile's lane-0 subsequence from its entry and, while
+// the entries of its half leave lane i's subsequence at different exits,
+// lane i + 1's subsequence from its own exit, up to lane kProbeLanes - 1.
+// When all entries of a half leave lane j at one exit, every later path of
+// the tile is independent of the entry: the record gets dep = j + 1, the
+// summed count of lanes 0..j and the starts of lanes 1..j per entry (for
+// the link step).  A half that finds no common exit within the probe, or
+// reaches the stream's end first, records dep = 0.  saved holds the two
+// tiles' step-1 results, cols the probe
+// lanes' units of both tiles (word w of lane i of tile h at
+// cols[(h * (S/32 + 1) + w - 1) * kProbeLanes + i]); every lane copies the
+// column it walks into its own TT column first, so the walks read
+// conflict-free.
+template <bool PAIR>
+__device__ void probe_pair(const SyncArgs &a, uint64_t t0, uint64_t t1, bool has1, const TileSync *saved,
+                           uint32_t *TTl, const uint32_t *cols, int lane, const SmemTable &st,
+                           const TableView &g, uint32_t sh)
+{
+    const uint32_t S = a.S, wps = S >> 5;
+    const bool hi = lane >= 32;
+    const uint32_t gent = static_cast<uint32_t>(lane) & 31u;
+    const uint64_t t = hi ? t1 : t0;
+    const bool mine = !hi || has1;
+    const bool probe = gent < g.L && mine;
+    SyncRec *rec = a.rec + t;
+    const uint32_t *src = cols + (hi ? (wps + 1) * kProbeLanes : 0u);
+    uint32_t cur = gent, sum = 0, dep = 0;
+    bool open = mine;                 // the half is still probing (uniform within a half)
+    wave_lds_sync();
+    for (uint32_t i = 0; i < kProbeLanes; ++i) {
+        const uint64_t k = (t << 6) + i;
+        const bool live = open && k < a.K;
+        open = live;
+        if (live)
+            for (uint32_t w = 1; w <= wps + 1; ++w)
+                TTl[w * 64] = src[(w - 1) * kProbeLanes + i];
+        uint32_t ex = 0, c = 0;
+        if (live && probe)
+            run_path<PAIR>(TTl, cur, lane_end(k, a.K, a.B, S), st, g, sh, ex, c);
+        const uint32_t ref = __shfl(ex, hi ? 32 : 0, 64);
+        const uint64_t diff = __builtin_amdgcn_ballot_w64(live && probe && ex != ref);
+        const bool same = (hi ? diff >> 32 : diff & 0xffffffffull) == 0;
+        if (live) {
+            sum += c;
+            cur = ex - S;
+            if (same) {
+                dep = i + 1;
+                open = false;
+            } else if (probe && i + 1 < kProbeLanes) {
+                rec->start_at[i][gent] = static_cast<uint8_t>(cur);
+            }
         }
-    } else {
-        // re-synced from the true entry with enough rounds: final
-        if (off_end)
-            atomicOr(a.status, kErrNoSync);
-        if (lane == 0) {
-            a.tot[t] = total;
-            a.rec[t].last_entry = static_cast<uint8_t>(last_exit - S);
+        if (__builtin_amdgcn_ballot_w64(open) == 0)
+            break;
+    }
+    if (mine) {
+        rec->count_at[gent] = static_cast<uint16_t>(probe ? sum : 0u);
+        if (gent == 0) {
+            const TileSync rs = saved[hi ? 1 : 0];
+            rec->last_entry = static_cast<uint8_t>(rs.last_exit - S);
+            rec->dep = static_cast<uint8_t>(dep);
+            a.tot[t] = rs.total;
+            // the tile's paths are final when its entry is (tile 0) or does
+            // not matter past the probed lanes, and the rounds converged;
+            // otherwise a later kernel decides
+            if (rs.off_end && rs.done && (t == 0 || dep != 0))
+                atomicOr(a.status, kErrNoSync);
         }
     }
-    return last_exit - S;
+}
+
+// Copies the first kProbeLanes lanes' units of the tile in TT (c0 = lane 0's
+// column) to cols in the probe's layout.
+__device__ __forceinline__ void save_probe_cols(uint32_t *cols, const uint32_t *c0, uint32_t ul, uint32_t wps)
+{
+    for (uint32_t f = ul; f < (wps + 1) * kProbeLanes; f += 64)
+        cols[f] = c0[(f / kProbeLanes + 1) * 64 + f % kProbeLanes];
 }
 
 template <int WPG, bool PAIR>
-__global__ __launch_bounds__(WPG * 64) void k_ss_sync(SyncArgs a)
+__global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_ss_sync(SyncArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const TableView &g = a.tab;
@@ -1411,14 +1488,44 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_sync(SyncArgs a)
     const int lane = threadIdx.x & 63;
     const int wv = wave_index();
     const uint32_t wps = a.S >> 5;
-    uint32_t *TTl = tt_of(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S), lane);
+    unsigned char *area = smem + table_lds_bytes(g.k1) + wv * sync_wave_bytes(a.S);
+    uint32_t *TTl = tt_of(area, lane);
+    // the first kProbeLanes lanes' units of the pair's two tiles (the
+    // probe's layout), then the two tiles' step-1 results
+    uint32_t *cols = reinterpret_cast<uint32_t *>(area + wave_units_bytes(a.S));
+    TileSync *saved = reinterpret_cast<TileSync *>(cols + 2 * kProbeLanes * (wps + 1));
+    const uint32_t *c0 = TTl - lane;                   // lane 0's column
     const uint32_t sh = 32 - g.k1;
-    const uint64_t tstride = static_cast<uint64_t>(gridDim.x) * WPG;
-    // (loading the next tile's units one tile ahead measured no faster here)
-    for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * WPG + wv; t < a.ntiles; t += tstride) {
-        load_units(TTl, a.words, (t << 6) + lane, a.K, wps);
+    const uint64_t npairs = (a.ntiles + 1) >> 1;
+    const uint64_t pstride = static_cast<uint64_t>(gridDim.x) * WPG;
+    // Tiles go in pairs so that one probe pass serves two tiles (at most 32
+    // entries each).  (Loading the next tile's units one tile ahead measured
+    // no faster here.)
+    for (uint64_t p = static_cast<uint64_t>(blockIdx.x) * WPG + wv; p < npairs; p += pstride) {
+        const uint64_t t0 = 2 * p, t1 = t0 + 1;
+        const bool has1 = t1 < a.ntiles;
+        const uint32_t ul = static_cast<uint32_t>(lane);
+        load_units(TTl, a.words, (t0 << 6) + lane, a.K, wps);
         wave_lds_sync();
-        sync_and_store<PAIR>(a, t, TTl, lane, 0u, true, kSyncRounds, st, g, sh);
+        // the step-1 results wait in LDS through the probe (keeping them in
+        // registers across the second sync and the probe costs occupancy)
+        {
+            const TileSync r0 = sync_core<PAIR>(a, t0, TTl, lane, 0u, kSyncRounds, st, g, sh);
+            save_probe_cols(cols, c0, ul, wps);
+            if (ul == 0)
+                saved[0] = r0;
+        }
+        if (has1) {
+            wave_lds_sync();
+            load_units(TTl, a.words, (t1 << 6) + lane, a.K, wps);
+            wave_lds_sync();
+            const TileSync r1 = sync_core<PAIR>(a, t1, TTl, lane, 0u, kSyncRounds, st, g, sh);
+            save_probe_cols(cols + kProbeLanes * (wps + 1), c0, ul, wps);
+            if (ul == 0)
+                saved[1] = r1;
+        }
+        wave_lds_sync();
+        probe_pair<PAIR>(a, t0, t1, has1, saved, TTl, cols, lane, st, g, sh);
         wave_lds_sync();
     }
 }
@@ -1477,7 +1584,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
             // the stream's last tile, final when its entry is (tile 0) or
             // does not matter: its last path must end on the stream end
             // (e is that lane's exit minus its end)
-            if ((t + 1) << 6 >= a.K && (t == 0 || a.rec[t].indep) && e != 0)
+            if ((t + 1) << 6 >= a.K && (t == 0 || a.rec[t].dep != 0) && e != 0)
                 atomicOr(a.status, kErrNoSync);
         }
         __syncthreads();
@@ -1525,23 +1632,27 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
     const uint32_t sh = 32 - g.k1;
     for (uint64_t u = static_cast<uint64_t>(blockIdx.x) * WPG + wv + 1; u < a.ntiles;
          u += static_cast<uint64_t>(gridDim.x) * WPG) {
-        // tile 0 starts at the true stream start; an entry-independent
-        // tile's last exit does not depend on its own entry
-        const bool prev_final = u == 1 || a.rec[u - 1].indep;
+        // tile 0 starts at the true stream start; a tile whose probe found a
+        // common exit has a last exit that does not depend on its entry
+        const bool prev_final = u == 1 || a.rec[u - 1].dep != 0;
         if (!prev_final)
             continue;                       // part of a run re-synced below
         uint32_t e = a.rec[u - 1].last_entry;
         for (uint64_t v = u; v < a.ntiles; ++v) {
-            if (a.rec[v].indep) {
+            const uint32_t dep = a.rec[v].dep;
+            if (dep) {
+                // lanes 0 .. dep-1 under the true entry e
                 if (lane == 0) {
                     a.gap_s[v << 6] = static_cast<uint8_t>(e);
                     a.tot[v] = a.tot[v] + a.rec[v].count_at[e] - a.rec[v].count_at[0];
+                } else if (static_cast<uint32_t>(lane) < dep) {
+                    a.gap_s[(v << 6) + lane] = a.rec[v].start_at[lane - 1][e];
                 }
                 break;
             }
             load_units(TTl, a.words, (v << 6) + lane, a.K, wps);
             wave_lds_sync();
-            e = sync_and_store<PAIR>(a, v, TTl, lane, e, false, kMaxRounds, st, g, sh);
+            e = resync_tile<PAIR>(a, v, TTl, lane, e, st, g, sh);
             wave_lds_sync();
         }
     }
@@ -2109,14 +2220,14 @@ hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, h
         return HD_ERR_DEVICE;
     const hd_stream_info &i = s->info;
     constexpr int kWpg = 8;
-    const uint32_t lds = table_lds_bytes(s->table->k1) + kWpg * wave_units_bytes(i.subseq_bits);
+    const uint32_t lds = table_lds_bytes(s->table->k1) + kWpg * sync_wave_bytes(i.subseq_bits);
     if (lds > dev->lds_per_block)
         return HD_ERR_UNSUPPORTED;
     // four groups of eight waves per CU measured faster here than three
     const uint32_t fit = std::max<uint32_t>(1, std::min<uint32_t>(static_cast<uint32_t>(dev->lds_per_cu / lds), 32 / kWpg));
     const uint64_t nt = ceil_div(i.n_subseq, 64);
-    const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nt, kWpg),
-                                                                                      uint64_t(dev->cus) * fit)));
+    const uint32_t grid = static_cast<uint32_t>(
+        std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(ceil_div(nt, 2), kWpg), uint64_t(dev->cus) * fit)));
     SyncArgs a;
     a.words = s->words;
     a.gap_s = w.gap_s;

@@ -134,6 +134,22 @@ def test_interleaved_runs_of_entry_dependent_tiles():
     _check_ss(case)
 
 
+@pytest.mark.parametrize("S,n", [(32, 200_000), (32, 77_777), (64, 150_001), (32, 1_234)])
+def test_entries_meeting_several_subsequences_later(S, n):
+    """Codes of about 8 bits with 32- and 64-bit subsequences: paths from
+    different entries of a tile often meet only in its second to fourth
+    subsequence, or later; stream sizes leave a ragged last tile."""
+    rng = np.random.default_rng(31 + n)
+    x = hdsynth.two_sided_geometric(rng, n, 0.98, 4096)
+    case = make_case(x, 4096, 20, S, 32)
+    _, _, sb = oracle.selfsync(case.enc.words, case.enc.n_bits, x.size, case.lengths, case.codes, S)
+    if n > 10_000:
+        assert ((sb > S) & (sb <= 4 * S)).sum() > sb.size // 10
+        assert (sb > 4 * S).sum() > 0
+    flush(f"entries meeting later: S={S} n={n} K={sb.size}")
+    _check_ss(case)
+
+
 def test_all_one_bit_codes_selfsync():
     rng = np.random.default_rng(5)
     x = rng.integers(0, 2, 400_000).astype(np.uint16)
