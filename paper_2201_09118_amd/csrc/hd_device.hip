@@ -1542,6 +1542,9 @@ template <int WPG, bool PAIR>
 __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const uint32_t n = *a.n_pending;
+    if (blockIdx.x >= n)
+        return;                              // no listed tile for this workgroup
     const TableView &g = a.tab;
     const SmemTable st = carve_table(smem, g.k1);
     load_table(st, g);
@@ -1553,8 +1556,10 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
     uint8_t *exo = units + wave_units_bytes(a.S);                       // [64][32] exit - E
     uint16_t *cnt = reinterpret_cast<uint16_t *>(exo + 64 * 32);        // [64][32]
     uint8_t *ent = reinterpret_cast<uint8_t *>(cnt + 64 * 32);          // [64] entry of each lane
+    uint8_t *bmap = ent + 64;                                           // [8][32] exit of 8 lanes per entry
+    uint8_t *bent = bmap + 8 * 32;                                      // [8] entry of each block of 8 lanes
     const uint32_t sh = 32 - g.k1;
-    const uint32_t n = *a.n_pending;
+    const uint32_t ne = min(g.L, 32u);
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const uint64_t t = a.pending[i];
         const uint64_t k = (t << 6) + lane;
@@ -1572,20 +1577,41 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
             cnt[lane * 32 + e] = static_cast<uint16_t>(c);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t e = 0;
-            for (uint32_t l = 0; l < 64; ++l) {
-                ent[l] = static_cast<uint8_t>(e);
+        // Chain the lane entries from lane 0's entry 0 in three steps of
+        // eight dependent reads: each block of eight lanes maps every entry
+        // to the block's exit, one thread chains the eight blocks, then each
+        // block walks its lanes from its own entry.
+        const uint32_t tid = threadIdx.x;
+        if (tid < 256 && (tid & 31u) < ne) {
+            const uint32_t b = tid >> 5;
+            uint32_t e = tid & 31u;
+            for (uint32_t l = 8 * b; l < 8 * b + 8; ++l)
                 if ((t << 6) + l < a.K)
                     e = exo[l * 32 + e];
+            bmap[tid] = static_cast<uint8_t>(e);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t e = 0;
+            for (uint32_t b = 0; b < 8; ++b) {
+                bent[b] = static_cast<uint8_t>(e);
+                e = bmap[b * 32 + e];
             }
-            ent[0] = 0;
             a.rec[t].last_entry = static_cast<uint8_t>(e);
             // the stream's last tile, final when its entry is (tile 0) or
             // does not matter: its last path must end on the stream end
             // (e is that lane's exit minus its end)
             if ((t + 1) << 6 >= a.K && (t == 0 || a.rec[t].dep != 0) && e != 0)
                 atomicOr(a.status, kErrNoSync);
+        }
+        __syncthreads();
+        if (tid < 8) {
+            uint32_t e = bent[tid];
+            for (uint32_t l = 8 * tid; l < 8 * tid + 8; ++l) {
+                ent[l] = static_cast<uint8_t>(e);
+                if ((t << 6) + l < a.K)
+                    e = exo[l * 32 + e];
+            }
         }
         __syncthreads();
         if (wv == 0) {
@@ -1603,7 +1629,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
 // LDS of the pending-tile kernel.
 __host__ __device__ __forceinline__ uint32_t pending_lds_bytes(uint32_t k1, uint32_t S)
 {
-    return table_lds_bytes(k1) + wave_units_bytes(S) + 64 * 32 * 3 + 64;
+    return table_lds_bytes(k1) + wave_units_bytes(S) + 64 * 32 * 3 + 64 + 8 * 32 + 16;
 }
 
 // Clears the pending-tile count and the status header word before the
@@ -1630,30 +1656,51 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
     const uint32_t wps = a.S >> 5;
     uint32_t *TTl = tt_of(smem + table_lds_bytes(g.k1) + wv * wave_units_bytes(a.S), lane);
     const uint32_t sh = 32 - g.k1;
-    for (uint64_t u = static_cast<uint64_t>(blockIdx.x) * WPG + wv + 1; u < a.ntiles;
-         u += static_cast<uint64_t>(gridDim.x) * WPG) {
+    // One lane per tile, 64 consecutive tiles per wavefront pass, so the
+    // record reads of all of them are in flight together.
+    for (uint64_t base = (static_cast<uint64_t>(blockIdx.x) * WPG + wv) << 6; base < a.ntiles;
+         base += static_cast<uint64_t>(gridDim.x) * WPG * 64) {
+        const uint64_t u = base + lane;
         // tile 0 starts at the true stream start; a tile whose probe found a
         // common exit has a last exit that does not depend on its entry
-        const bool prev_final = u == 1 || a.rec[u - 1].dep != 0;
-        if (!prev_final)
-            continue;                       // part of a run re-synced below
-        uint32_t e = a.rec[u - 1].last_entry;
-        for (uint64_t v = u; v < a.ntiles; ++v) {
-            const uint32_t dep = a.rec[v].dep;
-            if (dep) {
-                // lanes 0 .. dep-1 under the true entry e
-                if (lane == 0) {
-                    a.gap_s[v << 6] = static_cast<uint8_t>(e);
-                    a.tot[v] = a.tot[v] + a.rec[v].count_at[e] - a.rec[v].count_at[0];
-                } else if (static_cast<uint32_t>(lane) < dep) {
-                    a.gap_s[(v << 6) + lane] = a.rec[v].start_at[lane - 1][e];
+        bool head = false;
+        uint32_t e = 0, dep = 0;
+        if (u >= 1 && u < a.ntiles && (u == 1 || a.rec[u - 1].dep != 0)) {
+            head = true;
+            e = a.rec[u - 1].last_entry;
+            dep = a.rec[u].dep;
+        }
+        if (head && dep != 0) {
+            // lanes 0 .. dep-1 under the true entry e
+            const SyncRec *r = a.rec + u;
+            a.gap_s[u << 6] = static_cast<uint8_t>(e);
+            for (uint32_t i = 1; i < dep; ++i)
+                a.gap_s[(u << 6) + i] = r->start_at[i - 1][e];
+            a.tot[u] = a.tot[u] + r->count_at[e] - r->count_at[0];
+        }
+        // runs of tiles the probe left open, each from a final entry:
+        // re-synced in order by the whole wavefront
+        uint64_t runs = __builtin_amdgcn_ballot_w64(head && dep == 0);
+        while (runs != 0) {
+            const int l = __builtin_ctzll(runs);
+            runs &= runs - 1;
+            uint32_t ev = __shfl(e, l, 64);
+            for (uint64_t v = base + l; v < a.ntiles; ++v) {
+                const uint32_t dv = v == base + l ? 0u : a.rec[v].dep;
+                if (dv) {
+                    if (lane == 0) {
+                        a.gap_s[v << 6] = static_cast<uint8_t>(ev);
+                        a.tot[v] = a.tot[v] + a.rec[v].count_at[ev] - a.rec[v].count_at[0];
+                    } else if (static_cast<uint32_t>(lane) < dv) {
+                        a.gap_s[(v << 6) + lane] = a.rec[v].start_at[lane - 1][ev];
+                    }
+                    break;
                 }
-                break;
+                load_units(TTl, a.words, (v << 6) + lane, a.K, wps);
+                wave_lds_sync();
+                ev = resync_tile<PAIR>(a, v, TTl, lane, ev, st, g, sh);
+                wave_lds_sync();
             }
-            load_units(TTl, a.words, (v << 6) + lane, a.K, wps);
-            wave_lds_sync();
-            e = resync_tile<PAIR>(a, v, TTl, lane, e, st, g, sh);
-            wave_lds_sync();
         }
     }
 }
@@ -2207,7 +2254,10 @@ hd_status launch_sync(const SyncArgs &a, uint32_t grid, uint32_t lds, hipStream_
     hipLaunchKernelGGL((k_ss_sync<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
     hipLaunchKernelGGL((k_ss_pending<WPG, PAIR>), dim3(grid), dim3(WPG * 64),
                        pending_lds_bytes(a.tab.k1, a.S), stream, a);
-    hipLaunchKernelGGL((k_ss_link<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
+    // the link kernel takes 64 tiles per wavefront
+    const uint32_t lgrid = static_cast<uint32_t>(
+        std::max<uint64_t>(1, std::min<uint64_t>(grid, ceil_div(a.ntiles, uint64_t(64) * WPG))));
+    hipLaunchKernelGGL((k_ss_link<WPG, PAIR>), dim3(lgrid), dim3(WPG * 64), lds, stream, a);
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
 
