@@ -365,16 +365,39 @@ __device__ __forceinline__ uint32_t window_at(const uint32_t *TTl, uint32_t q)
 }
 
 // Codewords longer than the first level: canonical per-length limits,
-// searched from length l0 (from the slow first-level entry; at least k1 + 1).
+// searched from length l0 (from the slow first-level entry; at least k1 + 1),
+// STEP lengths at a time.  Under a canonical code a window under the limit
+// of length l is under the limit of every longer length, so the shortest
+// length whose limit the window is under is the codeword's.  A step of
+// several lengths issues their limit reads together: fewer dependent LDS
+// round trips for latency-bound walks, more reads and registers per step.
+template <int STEP = 1>
 __device__ __forceinline__ uint32_t decode_long(uint32_t v, uint32_t l0, uint32_t k1, uint32_t L,
                                              const uint64_t *lim, const int64_t *base,
                                              const uint32_t *syms, uint32_t *len_out)
 {
-    for (uint32_t l = max(l0, k1 + 1); l <= L; ++l) {
-        const uint64_t c = static_cast<uint64_t>(v) >> (32 - l);
-        if (c < lim[l]) {
-            *len_out = l;
-            return syms[static_cast<int64_t>(c) + base[l]];
+    if constexpr (STEP == 1) {
+        for (uint32_t l = max(l0, k1 + 1); l <= L; ++l) {
+            const uint64_t c = static_cast<uint64_t>(v) >> (32 - l);
+            if (c < lim[l]) {
+                *len_out = l;
+                return syms[static_cast<int64_t>(c) + base[l]];
+            }
+        }
+        *len_out = 0;
+        return 0;
+    }
+    for (uint32_t l = max(l0, k1 + 1); l <= L; l += STEP) {
+        uint32_t hit = 0;
+#pragma unroll
+        for (int j = STEP - 1; j >= 0; --j) {
+            const uint32_t lj = min(l + j, L);
+            if ((static_cast<uint64_t>(v) >> (32 - lj)) < lim[lj])
+                hit = lj;
+        }
+        if (hit) {
+            *len_out = hit;
+            return syms[static_cast<int64_t>(v >> (32 - hit)) + base[hit]];
         }
     }
     *len_out = 0;
@@ -467,11 +490,12 @@ __device__ __forceinline__ bool entry_group(uint32_t e, uint32_t k1, uint32_t &a
 
 // Slow first group of a window (first-level entry e): one codeword through
 // the per-length limits.
+template <int STEP = 1>
 __device__ __forceinline__ uint32_t slow_group(uint32_t v, uint32_t e, const SmemTable &st, const TableView &g,
                                                uint32_t &a, uint32_t &n, uint32_t &err)
 {
     uint32_t l;
-    const uint32_t s = decode_long(v, e & 0x3fu, g.k1, g.L, st.lim, st.base, g.syms, &l);
+    const uint32_t s = decode_long<STEP>(v, e & 0x3fu, g.k1, g.L, st.lim, st.base, g.syms, &l);
     if (l == 0) {
         err |= kErrBadCode;
         l = 1;
@@ -490,7 +514,7 @@ __device__ __forceinline__ uint32_t slow_group(uint32_t v, uint32_t e, const Sme
 // codewords (a group's second codeword, the second group, its second
 // codeword), and one correction after the loop drops those that start at or
 // after qe and moves q back to the first of them.
-template <bool PAIR>
+template <bool PAIR, int STEP = 1>
 __device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q, uint32_t qe,
                                                const SmemTable &st, const TableView &g, uint32_t sh,
                                                uint32_t &err)
@@ -517,7 +541,7 @@ __device__ __forceinline__ uint32_t count_walk(const uint32_t *TTl, uint32_t &q,
         if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fast1) != 0, 0)) {
             if (!fast1) {
                 uint32_t a, n;
-                slow_group(v, e1, st, g, a, n, err);
+                slow_group<STEP>(v, e1, st, g, a, n, err);
                 a1 = a;
                 l2 = 0;
             }
@@ -820,11 +844,10 @@ __device__ __forceinline__ uint32_t *tt_of(unsigned char *area, int lane)
 constexpr uint32_t kProbeLanes = 4;
 
 // A sync-kernel wavefront's LDS: the transposed units, then the first
-// kProbeLanes lanes' units of both tiles of a pair (the probe's inputs) and
-// the two tiles' step-1 results (TileSync, 12 bytes each).
+// kProbeLanes lanes' units of the tile being probed (the probe's inputs).
 __host__ __device__ __forceinline__ uint32_t sync_wave_bytes(uint32_t S)
 {
-    return wave_units_bytes(S) + 4 * 2 * kProbeLanes * ((S >> 5) + 1) + 32;
+    return wave_units_bytes(S) + 4 * kProbeLanes * ((S >> 5) + 1);
 }
 
 __host__ __device__ __forceinline__ uint32_t wave_area_bytes(uint32_t S, uint32_t stage, uint32_t sym_bytes = 2)
@@ -1207,21 +1230,33 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 // chained from lane 0), so no budget ever decides the result.
 //
 // Step 2 (inter-tile): the entry of tile u is the exit of tile u-1's last
-// lane.  Phase 1 assumes entry 0 and then walks the tile's first lanes from
-// every entry g < L, lane after lane, until all entries leave a lane j at the
-// same exit (at most kProbeLanes lanes): then only lanes 0..j depend on the
-// true entry (their starts and summed count per entry are recorded) and the
-// tile's later paths and last exit do not.  The link kernel fixes lanes
-// 0..j of every tile whose predecessor's exit is final, and re-syncs, in
+// lane.  Each wavefront syncs groups of consecutive tiles in order.  The
+// stream's first tile, and a tile whose predecessor in its group converged
+// and is exact or settled (its last exit is then final), are synced from
+// their true entry and are exact.  Any other tile (the first of a group, or
+// one after a tile left unconverged or unsettled) is synced from entry 0 and
+// probed:
+// the tile's first lanes are walked from every entry g < L, lane after lane,
+// until all entries leave a lane j at the same exit (at most kProbeLanes
+// lanes); then only lanes 0..j depend on the true entry (their starts and
+// summed count per entry are recorded) and the tile's later paths and last
+// exit do not (the tile is settled).  The link kernel fixes lanes 0..j of
+// every settled tile whose predecessor's exit is final, and re-syncs, in
 // order, runs of tiles whose entries did not converge within the probe
 // (codes that never resynchronize end up here).
 
 constexpr uint32_t kSyncRecBytes = 168;
+// Tiles a sync-kernel wavefront takes at a time, in order: the first is
+// probed, the others follow from their predecessors' exits.
+constexpr uint64_t kChainTiles = 2;
+// SyncRec::dep of an exact tile (synced from its true entry).
+constexpr uint8_t kDepExact = 255;
 
 struct SyncRec {
     uint8_t last_entry;       // next tile's lane-0 start implied by this tile's paths
-    uint8_t dep;              // lanes 0 .. dep-1 depend on the entry; 0: the probe found no common exit
-    uint8_t pad[6];
+    uint8_t dep;              // settled: lanes 0 .. dep-1 depend on the entry; 0: unsettled; kDepExact: exact
+    uint8_t entry_used;       // the lane-0 start the tile was synced from
+    uint8_t pad[5];
     uint16_t count_at[32];    // codewords of lanes 0 .. dep-1 from entry g
     uint8_t start_at[kProbeLanes - 1][32];   // start of lane i + 1 (< dep) from entry g
 };
@@ -1242,12 +1277,12 @@ struct SyncArgs {
 
 // Path from relative bit r: codewords starting before E, and the first start
 // at or after E (exit).
-template <bool PAIR>
+template <bool PAIR, int STEP = 1>
 __device__ __forceinline__ void run_path(const uint32_t *TTc, uint32_t r, uint32_t E, const SmemTable &st,
                                          const TableView &g, uint32_t sh, uint32_t &exit, uint32_t &cnt)
 {
     uint32_t q = r + 31, e = 0;
-    cnt = count_walk<PAIR>(TTc, q, E + 31, st, g, sh, e);
+    cnt = count_walk<PAIR, STEP>(TTc, q, E + 31, st, g, sh, e);
     exit = q - 31;
 }
 
@@ -1396,77 +1431,50 @@ __device__ uint32_t resync_tile(const SyncArgs &a, uint64_t t, const uint32_t *T
     return r.last_exit - a.S;
 }
 
-// The entry probe of two tiles in one pass: lanes 0..31 follow tile t0 from
-// entries 0..31, lanes 32..63 tile t1 (entries from L on are not followed).
-// Each lane walks the tile's lane-0 subsequence from its entry and, while
-// the entries of its half leave lane i's subsequence at different exits,
-// lane i + 1's subsequence from its own exit, up to lane kProbeLanes - 1.
-// When all entries of a half leave lane j at one exit, every later path of
-// the tile is independent of the entry: the record gets dep = j + 1, the
-// summed count of lanes 0..j and the starts of lanes 1..j per entry (for
-// the link step).  A half that finds no common exit within the probe, or
-// reaches the stream's end first, records dep = 0.  saved holds the two
-// tiles' step-1 results, cols the probe
-// lanes' units of both tiles (word w of lane i of tile h at
-// cols[(h * (S/32 + 1) + w - 1) * kProbeLanes + i]); every lane copies the
-// column it walks into its own TT column first, so the walks read
+// The entry probe of a tile synced from entry 0: lanes 0..31 follow the
+// tile from entries 0..31 (entries from L on are not followed).  Each walks
+// the tile's lane-0 subsequence from its entry and, while the entries leave
+// lane i's subsequence at different exits, lane i + 1's subsequence from its
+// own exit, up to lane kProbeLanes - 1.  When all entries leave lane j at one
+// exit, every later path of the tile is independent of the entry: returns
+// j + 1 and records the summed count of lanes 0..j and the starts of lanes
+// 1..j per entry (for the link step); 0 when no common exit is found within
+// the probe or the stream ends first.  cols holds the probe lanes' units
+// (word w of lane i at cols[(w - 1) * kProbeLanes + i]); every lane copies
+// the column it walks into its own TT column first, so the walks read
 // conflict-free.
 template <bool PAIR>
-__device__ void probe_pair(const SyncArgs &a, uint64_t t0, uint64_t t1, bool has1, const TileSync *saved,
-                           uint32_t *TTl, const uint32_t *cols, int lane, const SmemTable &st,
-                           const TableView &g, uint32_t sh)
+__device__ uint32_t probe_tile(const SyncArgs &a, uint64_t t, uint32_t *TTl, const uint32_t *cols, int lane,
+                               const SmemTable &st, const TableView &g, uint32_t sh)
 {
     const uint32_t S = a.S, wps = S >> 5;
-    const bool hi = lane >= 32;
-    const uint32_t gent = static_cast<uint32_t>(lane) & 31u;
-    const uint64_t t = hi ? t1 : t0;
-    const bool mine = !hi || has1;
-    const bool probe = gent < g.L && mine;
+    const uint32_t gent = static_cast<uint32_t>(lane);
+    const bool probe = gent < 32 && gent < g.L;
     SyncRec *rec = a.rec + t;
-    const uint32_t *src = cols + (hi ? (wps + 1) * kProbeLanes : 0u);
     uint32_t cur = gent, sum = 0, dep = 0;
-    bool open = mine;                 // the half is still probing (uniform within a half)
     wave_lds_sync();
     for (uint32_t i = 0; i < kProbeLanes; ++i) {
         const uint64_t k = (t << 6) + i;
-        const bool live = open && k < a.K;
-        open = live;
-        if (live)
-            for (uint32_t w = 1; w <= wps + 1; ++w)
-                TTl[w * 64] = src[(w - 1) * kProbeLanes + i];
+        if (k >= a.K)
+            break;                                   // the stream ends first: unsettled
+        for (uint32_t w = 1; w <= wps + 1; ++w)
+            TTl[w * 64] = cols[(w - 1) * kProbeLanes + i];
         uint32_t ex = 0, c = 0;
-        if (live && probe)
+        if (probe)
             run_path<PAIR>(TTl, cur, lane_end(k, a.K, a.B, S), st, g, sh, ex, c);
-        const uint32_t ref = __shfl(ex, hi ? 32 : 0, 64);
-        const uint64_t diff = __builtin_amdgcn_ballot_w64(live && probe && ex != ref);
-        const bool same = (hi ? diff >> 32 : diff & 0xffffffffull) == 0;
-        if (live) {
-            sum += c;
-            cur = ex - S;
-            if (same) {
-                dep = i + 1;
-                open = false;
-            } else if (probe && i + 1 < kProbeLanes) {
-                rec->start_at[i][gent] = static_cast<uint8_t>(cur);
-            }
-        }
-        if (__builtin_amdgcn_ballot_w64(open) == 0)
+        const uint32_t ref = __shfl(ex, 0, 64);
+        sum += c;
+        cur = ex - S;
+        if (__builtin_amdgcn_ballot_w64(probe && ex != ref) == 0) {
+            dep = i + 1;
             break;
-    }
-    if (mine) {
-        rec->count_at[gent] = static_cast<uint16_t>(probe ? sum : 0u);
-        if (gent == 0) {
-            const TileSync rs = saved[hi ? 1 : 0];
-            rec->last_entry = static_cast<uint8_t>(rs.last_exit - S);
-            rec->dep = static_cast<uint8_t>(dep);
-            a.tot[t] = rs.total;
-            // the tile's paths are final when its entry is (tile 0) or does
-            // not matter past the probed lanes, and the rounds converged;
-            // otherwise a later kernel decides
-            if (rs.off_end && rs.done && (t == 0 || dep != 0))
-                atomicOr(a.status, kErrNoSync);
         }
+        if (probe && i + 1 < kProbeLanes)
+            rec->start_at[i][gent] = static_cast<uint8_t>(cur);
     }
+    if (gent < 32)
+        rec->count_at[gent] = static_cast<uint16_t>(probe ? sum : 0u);
+    return dep;
 }
 
 // Copies the first kProbeLanes lanes' units of the tile in TT (c0 = lane 0's
@@ -1490,43 +1498,47 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
     const uint32_t wps = a.S >> 5;
     unsigned char *area = smem + table_lds_bytes(g.k1) + wv * sync_wave_bytes(a.S);
     uint32_t *TTl = tt_of(area, lane);
-    // the first kProbeLanes lanes' units of the pair's two tiles (the
-    // probe's layout), then the two tiles' step-1 results
+    // the probe lanes' units of the tile being probed (the probe's layout)
     uint32_t *cols = reinterpret_cast<uint32_t *>(area + wave_units_bytes(a.S));
-    TileSync *saved = reinterpret_cast<TileSync *>(cols + 2 * kProbeLanes * (wps + 1));
     const uint32_t *c0 = TTl - lane;                   // lane 0's column
     const uint32_t sh = 32 - g.k1;
-    const uint64_t npairs = (a.ntiles + 1) >> 1;
-    const uint64_t pstride = static_cast<uint64_t>(gridDim.x) * WPG;
-    // Tiles go in pairs so that one probe pass serves two tiles (at most 32
-    // entries each).  (Loading the next tile's units one tile ahead measured
-    // no faster here.)
-    for (uint64_t p = static_cast<uint64_t>(blockIdx.x) * WPG + wv; p < npairs; p += pstride) {
-        const uint64_t t0 = 2 * p, t1 = t0 + 1;
-        const bool has1 = t1 < a.ntiles;
-        const uint32_t ul = static_cast<uint32_t>(lane);
-        load_units(TTl, a.words, (t0 << 6) + lane, a.K, wps);
+    // groups of kChainTiles consecutive tiles, dealt to the wavefronts in
+    // turn (slow regions of a stream spread over many wavefronts)
+    const uint64_t ngroups = (a.ntiles + kChainTiles - 1) / kChainTiles;
+    const uint64_t gstride = static_cast<uint64_t>(gridDim.x) * WPG;
+    for (uint64_t gi = static_cast<uint64_t>(blockIdx.x) * WPG + wv; gi < ngroups; gi += gstride) {
+    const uint64_t t_begin = gi * kChainTiles;
+    const uint64_t t_end = min(a.ntiles, t_begin + kChainTiles);
+    // the entry of the next tile, when final (the stream's first tile starts
+    // at entry 0)
+    bool chained = t_begin == 0;
+    uint32_t entry = 0;
+    for (uint64_t t = t_begin; t < t_end; ++t) {
+        load_units(TTl, a.words, (t << 6) + lane, a.K, wps);
         wave_lds_sync();
-        // the step-1 results wait in LDS through the probe (keeping them in
-        // registers across the second sync and the probe costs occupancy)
-        {
-            const TileSync r0 = sync_core<PAIR>(a, t0, TTl, lane, 0u, kSyncRounds, st, g, sh);
-            save_probe_cols(cols, c0, ul, wps);
-            if (ul == 0)
-                saved[0] = r0;
+        const uint32_t e0 = chained ? entry : 0u;
+        const TileSync r = sync_core<PAIR>(a, t, TTl, lane, e0, kSyncRounds, st, g, sh);
+        uint32_t dep = kDepExact;
+        if (!chained) {
+            save_probe_cols(cols, c0, static_cast<uint32_t>(lane), wps);
+            dep = probe_tile<PAIR>(a, t, TTl, cols, lane, st, g, sh);
         }
-        if (has1) {
-            wave_lds_sync();
-            load_units(TTl, a.words, (t1 << 6) + lane, a.K, wps);
-            wave_lds_sync();
-            const TileSync r1 = sync_core<PAIR>(a, t1, TTl, lane, 0u, kSyncRounds, st, g, sh);
-            save_probe_cols(cols + kProbeLanes * (wps + 1), c0, ul, wps);
-            if (ul == 0)
-                saved[1] = r1;
+        if (lane == 0) {
+            SyncRec *rec = a.rec + t;
+            rec->last_entry = static_cast<uint8_t>(r.last_exit - a.S);
+            rec->dep = static_cast<uint8_t>(dep);
+            rec->entry_used = static_cast<uint8_t>(e0);
+            a.tot[t] = r.total;
+            // the tile's paths are final when its entry is, or does not
+            // matter past the probed lanes, and the rounds converged;
+            // otherwise a later kernel decides
+            if (r.off_end && r.done && dep != 0)
+                atomicOr(a.status, kErrNoSync);
         }
+        chained = r.done && dep != 0;
+        entry = r.last_exit - a.S;
         wave_lds_sync();
-        probe_pair<PAIR>(a, t0, t1, has1, saved, TTl, cols, lane, st, g, sh);
-        wave_lds_sync();
+    }
     }
 }
 
@@ -1538,6 +1550,12 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
 // in LDS), then one thread chains the entries from lane 0's entry 0 through
 // the lanes.  Lane 0's path and the tile record are already final.
 // LDS: table, the tile's units (one copy), exit and count tables.
+// The pending-tile kernel's wavefronts per workgroup (one workgroup per
+// listed tile: more wavefronts walk fewer entries each) and its slow-path
+// search step (its walks are latency-bound: few tiles, long codewords).
+constexpr int kPendingWpg = 16;
+constexpr int kPendingStep = 4;
+
 template <int WPG, bool PAIR>
 __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
 {
@@ -1572,12 +1590,12 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
         for (uint32_t e = wv; e < g.L && e < 32; e += WPG) {
             uint32_t ex = e, c = 0;
             if (act)
-                run_path<PAIR>(TTl, e, E, st, g, sh, ex, c);
+                run_path<PAIR, kPendingStep>(TTl, e, E, st, g, sh, ex, c);
             exo[lane * 32 + e] = static_cast<uint8_t>(ex - E);
             cnt[lane * 32 + e] = static_cast<uint16_t>(c);
         }
         __syncthreads();
-        // Chain the lane entries from lane 0's entry 0 in three steps of
+        // Chain the lane entries from the tile's entry in three steps of
         // eight dependent reads: each block of eight lanes maps every entry
         // to the block's exit, one thread chains the eight blocks, then each
         // block walks its lanes from its own entry.
@@ -1592,7 +1610,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
         }
         __syncthreads();
         if (tid == 0) {
-            uint32_t e = 0;
+            uint32_t e = a.rec[t].entry_used;
             for (uint32_t b = 0; b < 8; ++b) {
                 bent[b] = static_cast<uint8_t>(e);
                 e = bmap[b * 32 + e];
@@ -1626,7 +1644,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
     }
 }
 
-// LDS of the pending-tile kernel.
+// LDS of the pending-tile kernel (independent of its wavefront count).
 __host__ __device__ __forceinline__ uint32_t pending_lds_bytes(uint32_t k1, uint32_t S)
 {
     return table_lds_bytes(k1) + wave_units_bytes(S) + 64 * 32 * 3 + 64 + 8 * 32 + 16;
@@ -1670,7 +1688,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
             e = a.rec[u - 1].last_entry;
             dep = a.rec[u].dep;
         }
-        if (head && dep != 0) {
+        if (head && dep != 0 && dep != kDepExact) {
             // lanes 0 .. dep-1 under the true entry e
             const SyncRec *r = a.rec + u;
             a.gap_s[u << 6] = static_cast<uint8_t>(e);
@@ -1686,8 +1704,10 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
             runs &= runs - 1;
             uint32_t ev = __shfl(e, l, 64);
             for (uint64_t v = base + l; v < a.ntiles; ++v) {
+                // (a tile that follows an unsettled one was synced from entry
+                // 0, never chained, so it is settled or unsettled here)
                 const uint32_t dv = v == base + l ? 0u : a.rec[v].dep;
-                if (dv) {
+                if (dv != 0 && dv != kDepExact) {
                     if (lane == 0) {
                         a.gap_s[v << 6] = static_cast<uint8_t>(ev);
                         a.tot[v] = a.tot[v] + a.rec[v].count_at[ev] - a.rec[v].count_at[0];
@@ -2246,13 +2266,13 @@ hd_status launch_sync(const SyncArgs &a, uint32_t grid, uint32_t lds, hipStream_
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
             hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_link<WPG, PAIR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_pending<WPG, PAIR>),
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_pending<kPendingWpg, PAIR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
             return HD_ERR_DEVICE;
         attr_set = true;
     }
     hipLaunchKernelGGL((k_ss_sync<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
-    hipLaunchKernelGGL((k_ss_pending<WPG, PAIR>), dim3(grid), dim3(WPG * 64),
+    hipLaunchKernelGGL((k_ss_pending<kPendingWpg, PAIR>), dim3(grid), dim3(kPendingWpg * 64),
                        pending_lds_bytes(a.tab.k1, a.S), stream, a);
     // the link kernel takes 64 tiles per wavefront
     const uint32_t lgrid = static_cast<uint32_t>(
@@ -2277,7 +2297,7 @@ hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, h
     const uint32_t fit = std::max<uint32_t>(1, std::min<uint32_t>(static_cast<uint32_t>(dev->lds_per_cu / lds), 32 / kWpg));
     const uint64_t nt = ceil_div(i.n_subseq, 64);
     const uint32_t grid = static_cast<uint32_t>(
-        std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(ceil_div(nt, 2), kWpg), uint64_t(dev->cus) * fit)));
+        std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(ceil_div(nt, kChainTiles), kWpg), uint64_t(dev->cus) * fit)));
     SyncArgs a;
     a.words = s->words;
     a.gap_s = w.gap_s;
