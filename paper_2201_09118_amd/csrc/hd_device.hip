@@ -1550,14 +1550,16 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
 // in LDS), then one thread chains the entries from lane 0's entry 0 through
 // the lanes.  Lane 0's path and the tile record are already final.
 // LDS: table, the tile's units (one copy), exit and count tables.
-// The pending-tile kernel's wavefronts per workgroup (one workgroup per
-// listed tile: more wavefronts walk fewer entries each) and its slow-path
-// search step (its walks are latency-bound: few tiles, long codewords).
-constexpr int kPendingWpg = 16;
+// The pending-tile kernel's wavefronts per workgroup, and its slow-path
+// search step while every workgroup has at most one listed tile (then its
+// walks are latency-bound: a handful of tiles, typically of long codewords;
+// with many tiles per workgroup they are throughput-bound and search one
+// length at a time).
+constexpr int kPendingWpg = 8;
 constexpr int kPendingStep = 4;
 
 template <int WPG, bool PAIR>
-__global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
+__global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_ss_pending(SyncArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const uint32_t n = *a.n_pending;
@@ -1578,6 +1580,7 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
     uint8_t *bent = bmap + 8 * 32;                                      // [8] entry of each block of 8 lanes
     const uint32_t sh = 32 - g.k1;
     const uint32_t ne = min(g.L, 32u);
+    const bool few = n <= gridDim.x;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const uint64_t t = a.pending[i];
         const uint64_t k = (t << 6) + lane;
@@ -1589,8 +1592,12 @@ __global__ __launch_bounds__(WPG * 64) void k_ss_pending(SyncArgs a)
         const uint32_t E = lane_end(k, a.K, a.B, a.S);
         for (uint32_t e = wv; e < g.L && e < 32; e += WPG) {
             uint32_t ex = e, c = 0;
-            if (act)
-                run_path<PAIR, kPendingStep>(TTl, e, E, st, g, sh, ex, c);
+            if (act) {
+                if (few)
+                    run_path<PAIR, kPendingStep>(TTl, e, E, st, g, sh, ex, c);
+                else
+                    run_path<PAIR, 1>(TTl, e, E, st, g, sh, ex, c);
+            }
             exo[lane * 32 + e] = static_cast<uint8_t>(ex - E);
             cnt[lane * 32 + e] = static_cast<uint16_t>(c);
         }
