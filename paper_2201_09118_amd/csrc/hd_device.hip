@@ -775,6 +775,8 @@ constexpr uint32_t kMaxUnitsPerLane = 16;   // subsequences of at most 512 bits
 // Units per lane the tile-input registers are sized for: 4 covers
 // subsequences of up to 128 bits with 12 fewer registers than 16.
 constexpr uint32_t kSmallUnits = 4;
+// Units per lane of the middle tier: subsequences of up to 256 bits.
+constexpr uint32_t kMidUnits = 8;
 
 // One stream as the decode kernels see it.
 struct StreamDev {
@@ -2031,8 +2033,11 @@ uint32_t reg_waves_per_cu(const void *func)
 template <bool PAIR, typename T>
 const void *gap_kernel_of(uint32_t S)
 {
-    return S <= 32 * kSmallUnits ? reinterpret_cast<const void *>(&k_decode_gap<PAIR, kSmallUnits, false, T>)
-                                 : reinterpret_cast<const void *>(&k_decode_gap<PAIR, kMaxUnitsPerLane, false, T>);
+    if (S <= 32 * kSmallUnits)
+        return reinterpret_cast<const void *>(&k_decode_gap<PAIR, kSmallUnits, false, T>);
+    if (S <= 32 * kMidUnits)
+        return reinterpret_cast<const void *>(&k_decode_gap<PAIR, kMidUnits, false, T>);
+    return reinterpret_cast<const void *>(&k_decode_gap<PAIR, kMaxUnitsPerLane, false, T>);
 }
 
 // The decode kernel for a table format, subsequence size and symbol width.
@@ -2334,13 +2339,15 @@ hd_status launch_gap(const GapArgs &a, const Plan &p, hipStream_t stream)
 }
 
 template <typename T>
-hd_status launch_gap_as(const GapArgs &a, const Plan &p, bool pair, bool small, hipStream_t stream)
+hd_status launch_gap_as(const GapArgs &a, const Plan &p, bool pair, uint32_t S, hipStream_t stream)
 {
     if (pair)
-        return small ? launch_gap<true, kSmallUnits, T>(a, p, stream)
-                     : launch_gap<true, kMaxUnitsPerLane, T>(a, p, stream);
-    return small ? launch_gap<false, kSmallUnits, T>(a, p, stream)
-                 : launch_gap<false, kMaxUnitsPerLane, T>(a, p, stream);
+        return S <= 32 * kSmallUnits ? launch_gap<true, kSmallUnits, T>(a, p, stream)
+               : S <= 32 * kMidUnits ? launch_gap<true, kMidUnits, T>(a, p, stream)
+                                     : launch_gap<true, kMaxUnitsPerLane, T>(a, p, stream);
+    return S <= 32 * kSmallUnits ? launch_gap<false, kSmallUnits, T>(a, p, stream)
+           : S <= 32 * kMidUnits ? launch_gap<false, kMidUnits, T>(a, p, stream)
+                                 : launch_gap<false, kMaxUnitsPerLane, T>(a, p, stream);
 }
 
 // Enqueues the scan of per-tile totals (self-sync mode): off[0..M].
@@ -2474,13 +2481,12 @@ hd_status run_decode_kernel(const hd_dstream *s, void *out, hd_mode m, const hd_
     a.list = nullptr;
     a.n_list = 0;
     a.tab = view_of(s->table);
-    const bool small = i.subseq_bits <= 32 * kSmallUnits;
     const uint32_t wid = sym_bytes(i);
     if (wid == 1)
-        return launch_gap_as<uint8_t>(a, p, s->table->pair, small, stream);
+        return launch_gap_as<uint8_t>(a, p, s->table->pair, i.subseq_bits, stream);
     if (wid == 4)
-        return launch_gap_as<uint32_t>(a, p, s->table->pair, small, stream);
-    return launch_gap_as<uint16_t>(a, p, s->table->pair, small, stream);
+        return launch_gap_as<uint32_t>(a, p, s->table->pair, i.subseq_bits, stream);
+    return launch_gap_as<uint16_t>(a, p, s->table->pair, i.subseq_bits, stream);
 }
 
 }  // namespace
