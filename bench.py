@@ -35,14 +35,16 @@ SZ_SRC = os.path.join(ROOT, "paper_2201_09118_amd", "csrc", "hd_lorenzo.hip")
 
 
 GAP_KERNEL_SECTIONS = (("", "// Self-synchronization (Sec. III-B-2"),
-                       ("// Host entry points", "// Algorithm 2 host side"))
+                       ("// Host entry points", "// Self-sync host side"),
+                       ("// Gap-kernel launch (both modes)", "// Algorithm 2 host side"))
 
 
 def kernel_source_digest(kernel_src=KERNEL_SRC, sections=None):
     """sha256 of the source the gap-mode decode kernel is built and launched
     from: the decode table, device primitives and decode kernels (the file up
-    to the self-synchronization section) and the host section that plans and
-    launches it.  The self-sync, batch and other sections do not enter it."""
+    to the self-synchronization section) and the host code that plans and
+    launches it.  The self-sync kernels and their host side, the batch and
+    other sections do not enter it."""
     import hashlib
     text = open(kernel_src).read()
     h = hashlib.sha256()

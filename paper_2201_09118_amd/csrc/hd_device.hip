@@ -1552,21 +1552,24 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
 // in LDS), then one thread chains the entries from lane 0's entry 0 through
 // the lanes.  Lane 0's path and the tile record are already final.
 // LDS: table, the tile's units (one copy), exit and count tables.
-// The pending-tile kernel's wavefronts per workgroup, and its slow-path
-// search step while every workgroup has at most one listed tile (then its
-// walks are latency-bound: a handful of tiles, typically of long codewords;
-// with many tiles per workgroup they are throughput-bound and search one
-// length at a time).
+// The pending-tile kernel comes in two forms, launched one after the other
+// with one grid; only the one that fits the count of listed tiles works.
+// While every workgroup has at most one tile (FEW), its walks are
+// latency-bound (a handful of tiles, typically of long codewords): 16
+// wavefronts share a tile's entries and search the per-length limits four
+// lengths per step.  With more tiles they are throughput-bound: 8 wavefronts
+// per tile at full occupancy, one length per step.
+constexpr int kPendingWpgFew = 16;
 constexpr int kPendingWpg = 8;
 constexpr int kPendingStep = 4;
 
-template <int WPG, bool PAIR>
+template <int WPG, bool PAIR, bool FEW>
 __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_ss_pending(SyncArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const uint32_t n = *a.n_pending;
-    if (blockIdx.x >= n)
-        return;                              // no listed tile for this workgroup
+    if (blockIdx.x >= n || (n <= gridDim.x) != FEW)
+        return;                              // no listed tile for this workgroup, or the other form's count
     const TableView &g = a.tab;
     const SmemTable st = carve_table(smem, g.k1);
     load_table(st, g);
@@ -1582,7 +1585,6 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
     uint8_t *bent = bmap + 8 * 32;                                      // [8] entry of each block of 8 lanes
     const uint32_t sh = 32 - g.k1;
     const uint32_t ne = min(g.L, 32u);
-    const bool few = n <= gridDim.x;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const uint64_t t = a.pending[i];
         const uint64_t k = (t << 6) + lane;
@@ -1594,12 +1596,8 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
         const uint32_t E = lane_end(k, a.K, a.B, a.S);
         for (uint32_t e = wv; e < g.L && e < 32; e += WPG) {
             uint32_t ex = e, c = 0;
-            if (act) {
-                if (few)
-                    run_path<PAIR, kPendingStep>(TTl, e, E, st, g, sh, ex, c);
-                else
-                    run_path<PAIR, 1>(TTl, e, E, st, g, sh, ex, c);
-            }
+            if (act)
+                run_path<PAIR, FEW ? kPendingStep : 1>(TTl, e, E, st, g, sh, ex, c);
             exo[lane * 32 + e] = static_cast<uint8_t>(ex - E);
             cnt[lane * 32 + e] = static_cast<uint16_t>(c);
         }
@@ -2234,6 +2232,10 @@ size_t scan_ws_bytes(uint64_t M)
     return kWsStatusBytes + align_up(8 * (M + 1), 256) + align_up(8 * nblk, 256);
 }
 
+// ------------------------------------------------------------------------
+// Self-sync host side (workspace, launches of the synchronization kernels)
+// ------------------------------------------------------------------------
+
 // Self-sync workspace: the gap-mode part sized for one chunk per tile, then
 // the found sync points, per-tile totals and per-tile records.
 struct SyncWs {
@@ -2278,14 +2280,19 @@ hd_status launch_sync(const SyncArgs &a, uint32_t grid, uint32_t lds, hipStream_
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
             hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_link<WPG, PAIR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_pending<kPendingWpg, PAIR>),
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_pending<kPendingWpgFew, PAIR, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_pending<kPendingWpg, PAIR, false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
             return HD_ERR_DEVICE;
         attr_set = true;
     }
     hipLaunchKernelGGL((k_ss_sync<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
-    hipLaunchKernelGGL((k_ss_pending<kPendingWpg, PAIR>), dim3(grid), dim3(kPendingWpg * 64),
-                       pending_lds_bytes(a.tab.k1, a.S), stream, a);
+    const uint32_t plds = pending_lds_bytes(a.tab.k1, a.S);
+    hipLaunchKernelGGL((k_ss_pending<kPendingWpgFew, PAIR, true>), dim3(grid), dim3(kPendingWpgFew * 64), plds,
+                       stream, a);
+    hipLaunchKernelGGL((k_ss_pending<kPendingWpg, PAIR, false>), dim3(grid), dim3(kPendingWpg * 64), plds, stream,
+                       a);
     // the link kernel takes 64 tiles per wavefront
     const uint32_t lgrid = static_cast<uint32_t>(
         std::max<uint64_t>(1, std::min<uint64_t>(grid, ceil_div(a.ntiles, uint64_t(64) * WPG))));
@@ -2327,6 +2334,10 @@ hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, h
     return s->table->pair ? launch_sync<kWpg, true>(a, grid, lds, stream)
                           : launch_sync<kWpg, false>(a, grid, lds, stream);
 }
+
+// ------------------------------------------------------------------------
+// Gap-kernel launch (both modes)
+// ------------------------------------------------------------------------
 
 template <bool PAIR, uint32_t MAXU, typename T = uint16_t>
 hd_status launch_gap(const GapArgs &a, const Plan &p, hipStream_t stream)
