@@ -1549,8 +1549,9 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
 // self-synchronize, such as long runs of one codeword, where rounds would
 // fix one lane at a time).  One workgroup per tile: its wavefronts walk
 // every lane's subsequence from every entry g < L (exit and count per entry,
-// in LDS), then one thread chains the entries from lane 0's entry 0 through
-// the lanes.  Lane 0's path and the tile record are already final.
+// in LDS), then the lane entries are chained through those tables from the
+// entry the tile was synced from (0, or its predecessor's exit for a
+// chained tile); the tile's probe record, if any, is already written.
 // LDS: table, the tile's units (one copy), exit and count tables.
 // The pending-tile kernel comes in two forms, launched one after the other
 // with one grid; only the one that fits the count of listed tiles works.
@@ -1668,6 +1669,10 @@ __global__ void k_ss_clear(uint32_t *n_pending, uint32_t *status)
     }
 }
 
+// Step 2's link: one lane per tile fixes the entry-dependent lanes of every
+// settled tile whose predecessor's last exit is final; each run of unsettled
+// tiles from a final entry is re-synced in order by the wavefront that holds
+// its first tile.
 template <int WPG, bool PAIR>
 __global__ __launch_bounds__(WPG * 64) void k_ss_link(SyncArgs a)
 {
