@@ -1509,38 +1509,38 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
     const uint64_t ngroups = (a.ntiles + kChainTiles - 1) / kChainTiles;
     const uint64_t gstride = static_cast<uint64_t>(gridDim.x) * WPG;
     for (uint64_t gi = static_cast<uint64_t>(blockIdx.x) * WPG + wv; gi < ngroups; gi += gstride) {
-    const uint64_t t_begin = gi * kChainTiles;
-    const uint64_t t_end = min(a.ntiles, t_begin + kChainTiles);
-    // the entry of the next tile, when final (the stream's first tile starts
-    // at entry 0)
-    bool chained = t_begin == 0;
-    uint32_t entry = 0;
-    for (uint64_t t = t_begin; t < t_end; ++t) {
-        load_units(TTl, a.words, (t << 6) + lane, a.K, wps);
-        wave_lds_sync();
-        const uint32_t e0 = chained ? entry : 0u;
-        const TileSync r = sync_core<PAIR>(a, t, TTl, lane, e0, kSyncRounds, st, g, sh);
-        uint32_t dep = kDepExact;
-        if (!chained) {
-            save_probe_cols(cols, c0, static_cast<uint32_t>(lane), wps);
-            dep = probe_tile<PAIR>(a, t, TTl, cols, lane, st, g, sh);
+        const uint64_t t_begin = gi * kChainTiles;
+        const uint64_t t_end = min(a.ntiles, t_begin + kChainTiles);
+        // the entry of the next tile, when final (the stream's first tile starts
+        // at entry 0)
+        bool chained = t_begin == 0;
+        uint32_t entry = 0;
+        for (uint64_t t = t_begin; t < t_end; ++t) {
+            load_units(TTl, a.words, (t << 6) + lane, a.K, wps);
+            wave_lds_sync();
+            const uint32_t e0 = chained ? entry : 0u;
+            const TileSync r = sync_core<PAIR>(a, t, TTl, lane, e0, kSyncRounds, st, g, sh);
+            uint32_t dep = kDepExact;
+            if (!chained) {
+                save_probe_cols(cols, c0, static_cast<uint32_t>(lane), wps);
+                dep = probe_tile<PAIR>(a, t, TTl, cols, lane, st, g, sh);
+            }
+            if (lane == 0) {
+                SyncRec *rec = a.rec + t;
+                rec->last_entry = static_cast<uint8_t>(r.last_exit - a.S);
+                rec->dep = static_cast<uint8_t>(dep);
+                rec->entry_used = static_cast<uint8_t>(e0);
+                a.tot[t] = r.total;
+                // the tile's paths are final when its entry is, or does not
+                // matter past the probed lanes, and the rounds converged;
+                // otherwise a later kernel decides
+                if (r.off_end && r.done && dep != 0)
+                    atomicOr(a.status, kErrNoSync);
+            }
+            chained = r.done && dep != 0;
+            entry = r.last_exit - a.S;
+            wave_lds_sync();
         }
-        if (lane == 0) {
-            SyncRec *rec = a.rec + t;
-            rec->last_entry = static_cast<uint8_t>(r.last_exit - a.S);
-            rec->dep = static_cast<uint8_t>(dep);
-            rec->entry_used = static_cast<uint8_t>(e0);
-            a.tot[t] = r.total;
-            // the tile's paths are final when its entry is, or does not
-            // matter past the probed lanes, and the rounds converged;
-            // otherwise a later kernel decides
-            if (r.off_end && r.done && dep != 0)
-                atomicOr(a.status, kErrNoSync);
-        }
-        chained = r.done && dep != 0;
-        entry = r.last_exit - a.S;
-        wave_lds_sync();
-    }
     }
 }
 
