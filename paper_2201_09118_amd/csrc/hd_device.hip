@@ -116,7 +116,10 @@ struct hd_table {
 namespace {
 
 constexpr uint32_t kDefaultLutBits = 12;      // pair-format tables
-constexpr uint32_t kDefaultLutBitsWide = 11;  // alphabets above 4096
+// Alphabets above 4096 (one-symbol entries): on the 2^18-symbol field of
+// 12.6-bit mean codes 12 bits measured best (kernel 0.542 / 0.479 / 0.532 /
+// 0.498 ms at 11 / 12 / 13 / 14 bits).
+constexpr uint32_t kDefaultLutBitsWide = 12;
 
 struct TableView {
     const uint32_t *lut;
