@@ -210,9 +210,10 @@ size_t hd_table_lds_bytes(const hd_table *t);
  * status bits of the synchronization phase; word 1: the number of per-
  * wavefront status slots the last decode kernel wrote) and the slots
  * themselves.  In HD_MODE_SELF_SYNC it also holds the output-index scan of
- * the per-tile totals, the found sync points, per-tile records and the
- * pending-tile flags.  It needs no initialization: every word a call reads
- * is written by that call's kernels first.
+ * the per-tile totals, the found sync points, per-tile records (entry
+ * probe results) and the list of tiles left unconverged with its count.  It
+ * needs no initialization: every word a call reads is written by that call's
+ * kernels first.
  */
 hd_status hd_decode_workspace_size(const hd_dstream *s, hd_mode m, const hd_tune *tune,
                                    size_t *bytes);
