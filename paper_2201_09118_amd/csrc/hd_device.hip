@@ -1229,8 +1229,8 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 // re-derived) or the new path leaves the subsequence (a new exit).
 // Rounds end when a wavefront ballot finds no exit changed; after round r
 // lanes 0..r agree with the entry, so at most 64 rounds are ever needed.
-// The sync kernel spends at most kSyncRounds rounds on a tile and lists it
-// otherwise; the pending-tile kernel finishes listed tiles from per-entry
+// The sync kernel spends at most a per-stream budget of rounds on a tile
+// (sync_rounds) and lists it otherwise; the pending-tile kernel finishes listed tiles from per-entry
 // exit tables (every lane walked from every entry g < L, then the entries
 // chained from lane 0), so no budget ever decides the result.
 //
@@ -1278,6 +1278,7 @@ struct SyncArgs {
     TableView tab;
     uint64_t B, K, ntiles, n_words;
     uint32_t S;
+    uint32_t rounds;          // rounds the sync kernel spends on a tile before listing it
 };
 
 // Path from relative bit r: codewords starting before E, and the first start
@@ -1339,10 +1340,6 @@ __device__ __forceinline__ void load_units(uint32_t *TTl, const uint32_t *words,
 // Step 1 for one tile with lane 0 starting at e0.
 // Rounds of step 1: enough for any tile (after round r lanes 0..r are final).
 constexpr uint32_t kMaxRounds = 65;
-// Rounds the main sync kernel spends on a tile before handing it to the
-// pending-tile kernel.
-constexpr uint32_t kSyncRounds = 4;
-
 // Returns whether the rounds converged within max_rounds.
 template <bool PAIR>
 __device__ bool sync_tile(const uint32_t *TTl, int lane, bool act, uint32_t E, uint32_t S, uint32_t e0,
@@ -1522,7 +1519,7 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
             load_units(TTl, a.words, (t << 6) + lane, a.K, wps);
             wave_lds_sync();
             const uint32_t e0 = chained ? entry : 0u;
-            const TileSync r = sync_core<PAIR>(a, t, TTl, lane, e0, kSyncRounds, st, g, sh);
+            const TileSync r = sync_core<PAIR>(a, t, TTl, lane, e0, a.rounds, st, g, sh);
             uint32_t dep = kDepExact;
             if (!chained) {
                 save_probe_cols(cols, c0, static_cast<uint32_t>(lane), wps);
@@ -1548,7 +1545,7 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
 }
 
 // Finishes step 1 for the tiles the sync kernel left unconverged after
-// kSyncRounds rounds (listed in a.pending; typically streams that do not
+// its round budget (listed in a.pending; typically streams that do not
 // self-synchronize, such as long runs of one codeword, where rounds would
 // fix one lane at a time).  One workgroup per tile: its wavefronts walk
 // every lane's subsequence from every entry g < L (exit and count per entry,
@@ -2308,6 +2305,21 @@ hd_status launch_sync(const SyncArgs &a, uint32_t grid, uint32_t lds, hipStream_
     return hipGetLastError() == hipSuccess ? HD_OK : HD_ERR_DEVICE;
 }
 
+// Rounds the sync kernel spends on a tile before listing it for the
+// pending-tile kernel (which finishes any tile exactly, so the budget only
+// trades time).  Longer codes resynchronize later: a tile needs more rounds,
+// and listing it costs L walks per lane.  Measured budgets (whole self-sync
+// step): config 2 (mean code 5.9 bits) 2 / 3 / 4 / 6 / 8 rounds 0.333 /
+// 0.336 / 0.358 / 0.394 / 0.418 ms; config 3 (7.4 bits) 3 / 4 / 6 / 8 / 12
+// rounds 0.992 / 0.985 / 0.964 / 0.975 / 0.969 ms; the config-2 field as
+// uint32 codes (12.6 bits) 4 / 6 / 8 / 12 / 16 rounds 7.90 / 5.30 / 4.15 /
+// 3.66 / 3.64 ms.
+uint32_t sync_rounds(const hd_stream_info &i)
+{
+    const double lbar = i.n_symbols ? double(i.n_bits) / double(i.n_symbols) : 1.0;
+    return lbar < 7.0 ? 3u : lbar < 10.0 ? 6u : 16u;
+}
+
 // Enqueues steps 1-2 of self-synchronization: sync points into gap_s and
 // per-tile codeword totals into tot.
 hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, hipStream_t stream)
@@ -2339,6 +2351,7 @@ hd_status enqueue_sync(const hd_dstream *s, const SyncWs &w, uint32_t *status, h
     a.ntiles = nt;
     a.n_words = i.n_words;
     a.S = i.subseq_bits;
+    a.rounds = sync_rounds(i);
     return s->table->pair ? launch_sync<kWpg, true>(a, grid, lds, stream)
                           : launch_sync<kWpg, false>(a, grid, lds, stream);
 }

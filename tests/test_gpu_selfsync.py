@@ -73,8 +73,9 @@ def test_fixed_length_code_never_synchronizes():
 @pytest.mark.parametrize("S", [32, 96, 256, 512])
 def test_unconverged_tiles_at_every_subsequence_size(S):
     """3-bit fixed-length code at several subsequence sizes and a ragged
-    length: tiles stay unconverged after the sync kernel's four rounds
-    (kSyncRounds) and are finished from per-entry exit tables."""
+    length: tiles stay unconverged after the sync kernel's round budget
+    (three rounds for codes this short) and are finished from per-entry exit
+    tables."""
     rng = np.random.default_rng(30 + S)
     x = rng.integers(0, 8, 200_003).astype(np.uint16)
     flush(f"unconverged tiles S={S}")
