@@ -1553,31 +1553,42 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
 // entry the tile was synced from (0, or its predecessor's exit for a
 // chained tile); the tile's probe record, if any, is already written.
 // LDS: table, the tile's units (one copy), exit and count tables.
-// The pending-tile kernel comes in two forms, launched one after the other
-// with one grid; only the one that fits the count of listed tiles works.
-// While every workgroup has at most one tile (FEW), its walks are
-// latency-bound (a handful of tiles, typically of long codewords): 16
-// wavefronts share a tile's entries and search the per-length limits four
-// lengths per step.  With more tiles they are throughput-bound: 8 wavefronts
-// per tile at full occupancy, one length per step.
-constexpr int kPendingWpgFew = 16;
-constexpr int kPendingWpg = 8;
+// While every workgroup has at most one listed tile (few), the walks are
+// latency-bound (a handful of tiles, typically of long codewords): the
+// workgroup's 16 wavefronts share one tile's entries and search the
+// per-length limits four lengths per step.  With more tiles they are
+// throughput-bound: each half of the workgroup (8 wavefronts) takes its own
+// tile, one length per step.
+constexpr int kPendingWaves = 16;
 constexpr int kPendingStep = 4;
 
-template <int WPG, bool PAIR, bool FEW>
-__global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_ss_pending(SyncArgs a)
+// LDS of one tile in the pending-tile kernel: its units (one copy), exit
+// and count tables, lane entries and the blocked chain's maps.
+__host__ __device__ __forceinline__ uint32_t pending_tile_bytes(uint32_t S)
+{
+    return (wave_units_bytes(S) + 64 * 32 * 3 + 64 + 8 * 32 + 8 + 15u) & ~15u;
+}
+
+template <bool PAIR>
+__global__ __launch_bounds__(kPendingWaves * 64) __attribute__((amdgpu_waves_per_eu(8))) void k_ss_pending(SyncArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const uint32_t n = *a.n_pending;
-    if (blockIdx.x >= n || (n <= gridDim.x) != FEW)
-        return;                              // no listed tile for this workgroup, or the other form's count
+    const bool few = n <= gridDim.x;
+    const uint32_t per = few ? 1u : 2u;          // tiles per workgroup pass
+    if (blockIdx.x * per >= n)
+        return;                                  // no listed tile for this workgroup
     const TableView &g = a.tab;
     const SmemTable st = carve_table(smem, g.k1);
     load_table(st, g);
     const int lane = threadIdx.x & 63;
-    const int wv = wave_index();
+    const uint32_t wv = static_cast<uint32_t>(wave_index());
+    const uint32_t half = few ? 0u : wv / (kPendingWaves / 2);
+    const uint32_t hw = few ? wv : wv % (kPendingWaves / 2);          // wavefront within the half
+    const uint32_t hwaves = few ? kPendingWaves : kPendingWaves / 2;
+    const uint32_t htid = threadIdx.x - half * (kPendingWaves / 2) * 64;
     const uint32_t wps = a.S >> 5;
-    unsigned char *units = smem + table_lds_bytes(g.k1);
+    unsigned char *units = smem + table_lds_bytes(g.k1) + half * pending_tile_bytes(a.S);
     const uint32_t *TTl = tt_of(units, lane);
     uint8_t *exo = units + wave_units_bytes(a.S);                       // [64][32] exit - E
     uint16_t *cnt = reinterpret_cast<uint16_t *>(exo + 64 * 32);        // [64][32]
@@ -1586,38 +1597,47 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
     uint8_t *bent = bmap + 8 * 32;                                      // [8] entry of each block of 8 lanes
     const uint32_t sh = 32 - g.k1;
     const uint32_t ne = min(g.L, 32u);
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const uint64_t t = a.pending[i];
+    // every thread runs every pass and barrier; a half without a tile in the
+    // last pass only waits
+    for (uint32_t pass = blockIdx.x; pass * per < n; pass += gridDim.x) {
+        const uint32_t i = pass * per + half;
+        const bool have = i < n;
+        const uint64_t t = have ? a.pending[i] : 0u;
         const uint64_t k = (t << 6) + lane;
-        const bool act = k < a.K;
-        __syncthreads();                     // the previous tile is done with the LDS
-        if (wv == 0)
+        const bool act = have && k < a.K;
+        __syncthreads();                     // the previous tiles are done with the LDS
+        if (hw == 0 && have)
             load_units(tt_of(units, lane), a.words, k, a.K, wps);
         __syncthreads();
         const uint32_t E = lane_end(k, a.K, a.B, a.S);
-        for (uint32_t e = wv; e < g.L && e < 32; e += WPG) {
-            uint32_t ex = e, c = 0;
-            if (act)
-                run_path<PAIR, FEW ? kPendingStep : 1>(TTl, e, E, st, g, sh, ex, c);
-            exo[lane * 32 + e] = static_cast<uint8_t>(ex - E);
-            cnt[lane * 32 + e] = static_cast<uint16_t>(c);
+        if (have) {
+            for (uint32_t e = hw; e < ne; e += hwaves) {
+                uint32_t ex = e, c = 0;
+                if (act) {
+                    if (few)
+                        run_path<PAIR, kPendingStep>(TTl, e, E, st, g, sh, ex, c);
+                    else
+                        run_path<PAIR, 1>(TTl, e, E, st, g, sh, ex, c);
+                }
+                exo[lane * 32 + e] = static_cast<uint8_t>(ex - E);
+                cnt[lane * 32 + e] = static_cast<uint16_t>(c);
+            }
         }
         __syncthreads();
         // Chain the lane entries from the tile's entry in three steps of
         // eight dependent reads: each block of eight lanes maps every entry
         // to the block's exit, one thread chains the eight blocks, then each
         // block walks its lanes from its own entry.
-        const uint32_t tid = threadIdx.x;
-        if (tid < 256 && (tid & 31u) < ne) {
-            const uint32_t b = tid >> 5;
-            uint32_t e = tid & 31u;
+        if (have && htid < 256 && (htid & 31u) < ne) {
+            const uint32_t b = htid >> 5;
+            uint32_t e = htid & 31u;
             for (uint32_t l = 8 * b; l < 8 * b + 8; ++l)
                 if ((t << 6) + l < a.K)
                     e = exo[l * 32 + e];
-            bmap[tid] = static_cast<uint8_t>(e);
+            bmap[htid] = static_cast<uint8_t>(e);
         }
         __syncthreads();
-        if (tid == 0) {
+        if (have && htid == 0) {
             uint32_t e = a.rec[t].entry_used;
             for (uint32_t b = 0; b < 8; ++b) {
                 bent[b] = static_cast<uint8_t>(e);
@@ -1631,16 +1651,16 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
                 atomicOr(a.status, kErrNoSync);
         }
         __syncthreads();
-        if (tid < 8) {
-            uint32_t e = bent[tid];
-            for (uint32_t l = 8 * tid; l < 8 * tid + 8; ++l) {
+        if (have && htid < 8) {
+            uint32_t e = bent[htid];
+            for (uint32_t l = 8 * htid; l < 8 * htid + 8; ++l) {
                 ent[l] = static_cast<uint8_t>(e);
                 if ((t << 6) + l < a.K)
                     e = exo[l * 32 + e];
             }
         }
         __syncthreads();
-        if (wv == 0) {
+        if (have && hw == 0) {
             const uint32_t e = ent[lane];
             const uint32_t c = act ? cnt[lane * 32 + e] : 0u;
             if (act)
@@ -1652,10 +1672,10 @@ __global__ __launch_bounds__(WPG * 64) __attribute__((amdgpu_waves_per_eu(8))) v
     }
 }
 
-// LDS of the pending-tile kernel (independent of its wavefront count).
+// LDS of the pending-tile kernel: the table and two tiles.
 __host__ __device__ __forceinline__ uint32_t pending_lds_bytes(uint32_t k1, uint32_t S)
 {
-    return table_lds_bytes(k1) + wave_units_bytes(S) + 64 * 32 * 3 + 64 + 8 * 32 + 16;
+    return table_lds_bytes(k1) + 2 * pending_tile_bytes(S);
 }
 
 // Clears the pending-tile count and the status header word before the
@@ -2285,19 +2305,14 @@ hd_status launch_sync(const SyncArgs &a, uint32_t grid, uint32_t lds, hipStream_
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
             hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_link<WPG, PAIR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_pending<kPendingWpgFew, PAIR, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_pending<kPendingWpg, PAIR, false>),
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ss_pending<PAIR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
             return HD_ERR_DEVICE;
         attr_set = true;
     }
     hipLaunchKernelGGL((k_ss_sync<WPG, PAIR>), dim3(grid), dim3(WPG * 64), lds, stream, a);
-    const uint32_t plds = pending_lds_bytes(a.tab.k1, a.S);
-    hipLaunchKernelGGL((k_ss_pending<kPendingWpgFew, PAIR, true>), dim3(grid), dim3(kPendingWpgFew * 64), plds,
-                       stream, a);
-    hipLaunchKernelGGL((k_ss_pending<kPendingWpg, PAIR, false>), dim3(grid), dim3(kPendingWpg * 64), plds, stream,
-                       a);
+    hipLaunchKernelGGL((k_ss_pending<PAIR>), dim3(grid), dim3(kPendingWaves * 64),
+                       pending_lds_bytes(a.tab.k1, a.S), stream, a);
     // the link kernel takes 64 tiles per wavefront
     const uint32_t lgrid = static_cast<uint32_t>(
         std::max<uint64_t>(1, std::min<uint64_t>(grid, ceil_div(a.ntiles, uint64_t(64) * WPG))));
