@@ -151,6 +151,23 @@ def test_entries_meeting_several_subsequences_later(S, n):
     _check_ss(case)
 
 
+@pytest.mark.parametrize("i", range(12))
+def test_long_code_streams_selfsync(i):
+    """Mean code lengths from 6.7 to 11.4 bits in 32- to 128-bit subsequences:
+    all three round budgets of the sync kernel (below 7, 10 and above), many
+    tiles listed for the pending-tile kernel (few and many per workgroup) and
+    first tiles of groups that the entry probe leaves unsettled."""
+    S = [32, 64, 96, 128][i % 4]
+    A = [4096, 65536, 16384][i % 3]
+    r = [0.95, 0.98, 0.995, 0.998][(i // 3) % 4]
+    n = [3001, 54321, 200003, 99999][i % 4]
+    x = hdsynth.two_sided_geometric(np.random.default_rng(1900 + i), n, r, A)
+    used = int((np.bincount(x, minlength=A) > 0).sum())
+    L = max(int(np.ceil(np.log2(max(used, 2)))), [18, 22, 27][i % 3])
+    flush(f"long-code self-sync i={i} S={S} A={A} r={r} n={n} L={L}")
+    _check_ss(make_case(x, A, L, S, 32))
+
+
 def test_all_one_bit_codes_selfsync():
     rng = np.random.default_rng(5)
     x = rng.integers(0, 2, 400_000).astype(np.uint16)
