@@ -1230,9 +1230,10 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 // Rounds end when a wavefront ballot finds no exit changed; after round r
 // lanes 0..r agree with the entry, so at most 64 rounds are ever needed.
 // The sync kernel spends at most a per-stream budget of rounds on a tile
-// (sync_rounds) and lists it otherwise; the pending-tile kernel finishes listed tiles from per-entry
-// exit tables (every lane walked from every entry g < L, then the entries
-// chained from lane 0), so no budget ever decides the result.
+// (sync_rounds) and lists it otherwise; the pending-tile kernel finishes
+// listed tiles from per-entry exit tables (every lane walked from every
+// entry g < L, then the entries chained from the tile's entry), so no
+// budget ever decides the result.
 //
 // Step 2 (inter-tile): the entry of tile u is the exit of tile u-1's last
 // lane.  Each wavefront syncs groups of consecutive tiles in order.  The
@@ -1240,8 +1241,7 @@ __global__ __launch_bounds__(1024) void k_decode_gap(GapArgs a)
 // and is exact or settled (its last exit is then final), are synced from
 // their true entry and are exact.  Any other tile (the first of a group, or
 // one after a tile left unconverged or unsettled) is synced from entry 0 and
-// probed:
-// the tile's first lanes are walked from every entry g < L, lane after lane,
+// probed: the tile's first lanes are walked from every entry g < L, lane after lane,
 // until all entries leave a lane j at the same exit (at most kProbeLanes
 // lanes); then only lanes 0..j depend on the true entry (their starts and
 // summed count per entry are recorded) and the tile's later paths and last
